@@ -1,0 +1,236 @@
+"""Pins of the oracle's time step against closed forms and invariants fixed by the
+paper (Sec. 2.1, 2.4, 3.1) and by textbook results. No GPU.
+
+* streaming and bounce-back moves, by hand on tiny lattices;
+* steady uniform states, conservation, dormant anomaly (invariants);
+* shear-wave viscosity nu = (1/omega - 1/2) T (Sec. 2.1, eq. nu), Galilean
+  invariance and isotropy on stretched lattices (Sec. 3.1);
+* the uncorrected control against the viscosity predicted by the paper's own
+  hydrodynamic limit without the counter term (Sec. 2.4, eq. momentum2 with
+  P*(1) = 0), linearised about the advection velocity:
+  nu_eff / nu = 1 + (c_x + c_y) / (4T), c_a = lam_a^2 - 3T - 3 U_a^2;
+* Poiseuille flow between halfway bounce-back walls (textbook closed form).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import inputs as I
+import oracle as O
+
+
+def random_state(p, seed, amp=0.02):
+    g = np.random.default_rng(seed)
+    grid = tuple(reversed(p.n))
+    rho = 1.0 + 0.05 * g.standard_normal(grid)
+    u = amp * g.standard_normal((p.D,) + grid)
+    f = O.equilibrium(rho, u, p.T, p.lam, p.c)
+    # non-equilibrium part so that every term of the step is exercised
+    return f * (1.0 + 0.01 * g.standard_normal(f.shape))
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_stream_moves_one_node(D):
+    n = (5, 4, 3)[:D]
+    p = O.Params(n=n)
+    c = p.c
+    grid = tuple(reversed(n))
+    for i in range(c.shape[0]):
+        f = np.zeros((c.shape[0],) + grid)
+        src = tuple(0 for _ in range(D))  # node at the origin
+        f[(i,) + src] = 1.0
+        g = O.stream(f, c, (False,) * D)
+        dst = tuple((-0 + int(c[i, D - 1 - ax])) % grid[ax] for ax in range(D))
+        assert g[(i,) + dst] == 1.0
+        assert g.sum() == 1.0
+
+
+def test_bounce_back_returns_at_same_node():
+    p = O.Params(n=(4, 3), walls=(False, True))
+    c = p.c
+    grid = (3, 4)
+    for i in range(9):
+        if c[i, 1] == 0:
+            continue
+        f = np.zeros((9,) + grid)
+        # population i leaving the boundary row it points out of
+        row = 0 if c[i, 1] == -1 else 2
+        f[i, row, 1] = 1.0
+        g = O.stream(f, c, p.walls)
+        opp = 8 - i
+        assert g[opp, row, 1] == 1.0
+        assert g.sum() == 1.0
+
+
+@pytest.mark.parametrize("D,lam,T,omega", [
+    (2, (1.0, 1.0), 1.0 / 3.0, 1.8),
+    (2, (2.0, 1.0), 0.45, 1.3),
+    (3, (1.0, 1.0, 1.0), 0.5, 1.9),
+    (3, (2.0, 1.0, 1.4), 0.3, 0.7),
+])
+@pytest.mark.parametrize("U", [0.0, 0.08])
+def test_uniform_states_are_steady(D, lam, T, omega, U):
+    n = (6, 5, 4)[:D]
+    p = O.Params(n=n, lam=lam, T=T, omega=omega)
+    fld = I.uniform(n, lam, u0=(U, -0.5 * U, 0.3 * U)[:D])
+    f0 = O.init_state(fld.rho, fld.u, p)
+    f = O.run(f0, p, 5)
+    np.testing.assert_allclose(f, f0, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_conservation_periodic(D):
+    n = (8, 6, 5)[:D]
+    p = O.Params(n=n, lam=(2.0, 1.0, 1.0)[:D], T=0.5, omega=1.7)
+    f = random_state(p, 1)
+    r0, j0 = O.moments(f, p.c, p.lam)
+    m0, J0 = r0.sum(), j0.reshape(D, -1).sum(axis=1)
+    for _ in range(10):
+        f = O.step(f, p)
+    r, j = O.moments(f, p.c, p.lam)
+    assert abs(r.sum() - m0) < 1e-12 * m0
+    np.testing.assert_allclose(j.reshape(D, -1).sum(axis=1), J0, rtol=0, atol=1e-12 * m0)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_conservation_walls_and_force(D):
+    n = (6, 8, 4)[:D]
+    g = (1e-4, 0.0, 2e-5)[:D]
+    # mass with bounce-back walls in y
+    p = O.Params(n=n, lam=(1.0, 1.0, 1.0)[:D], T=0.5, omega=1.6, walls=(False, True, False)[:D])
+    f = random_state(p, 2)
+    m0 = f.sum()
+    for _ in range(10):
+        f = O.step(f, p)
+    assert abs(f.sum() - m0) < 1e-12 * m0
+    # periodic + force: sum j grows by g sum(rho) per step, exactly
+    p = O.Params(n=n, lam=(2.0, 1.0, 1.0)[:D], T=0.5, omega=1.6, force=g)
+    f = random_state(p, 3)
+    for _ in range(5):
+        r0, j0 = O.moments(f, p.c, p.lam)
+        f = O.step(f, p)
+        r1, j1 = O.moments(f, p.c, p.lam)
+        dJ = j1.reshape(D, -1).sum(axis=1) - j0.reshape(D, -1).sum(axis=1)
+        np.testing.assert_allclose(dJ, np.array(g) * r0.sum(), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("T", [1.0 / 3.0, 0.5])
+def test_dormant_anomaly_axis_aligned_wave(T):
+    """Axis-aligned advected wave: the gradient terms vanish, so the extended step
+    equals the uncorrected one, rho stays 1 and u_x stays U0 (Sec. 3.1)."""
+    fld = I.shear_wave_axis((64, 64), U0=0.1, A=0.01)
+    pe = O.Params(n=(64, 64), T=T, omega=1.8, extended=True)
+    pc = O.Params(n=(64, 64), T=T, omega=1.8, extended=False)
+    fe = O.init_state(fld.rho, fld.u, pe)
+    fc = fe.copy()
+    for _ in range(100):
+        fe = O.step(fe, pe)
+        fc = O.step(fc, pc)
+    np.testing.assert_allclose(fe, fc, rtol=0, atol=1e-14)
+    rho, u = O.velocity(fe, pe)
+    assert np.abs(rho - 1.0).max() < 1e-13
+    assert np.abs(u[0] - 0.1).max() < 1e-13
+
+
+def fitted_ratio(n, lam, T, omega, U0, a0=1e-3, extended=True, steps=500, every=1):
+    fld = I.shear_wave_rotated(n, lam, U0, a0)
+    p = O.Params(n=n, lam=lam, T=T, omega=omega, extended=extended)
+    f0 = O.init_state(fld.rho, fld.u, p)
+    nu, _ = O.measure_viscosity(f0, p, fld.mode_k, fld.mode_dir, steps, every=every)
+    return nu / p.nu
+
+
+@pytest.mark.parametrize("T", [1.0 / 3.0, 0.5])
+def test_viscosity_axis_aligned(T):
+    """cfg: D2Q9 64x64, U0 = 0.1, A = 0.01, omega = 1.8: nu within 1% (Sec. 2.1, eq. nu)."""
+    fld = I.shear_wave_axis((64, 64), U0=0.1, A=0.01)
+    p = O.Params(n=(64, 64), T=T, omega=1.8)
+    f0 = O.init_state(fld.rho, fld.u, p)
+    nu, _ = O.measure_viscosity(f0, p, fld.mode_k, fld.mode_dir, 500, every=5)
+    assert abs(nu / p.nu - 1.0) < 1e-2
+
+
+@pytest.mark.parametrize("U0", [0.0, 0.1, 0.173])
+def test_galilean_invariance_rotated_cubic(U0):
+    """Rotated wave on the cubic lattice: nu independent of the advection speed (Sec. 3.1)."""
+    assert abs(fitted_ratio((64, 64), (1.0, 1.0), 1.0 / 3.0, 1.8, U0, every=5) - 1.0) < 1e-2
+
+
+def test_isotropy_stretched_converges():
+    """Stretched lam = (2, 1): nu recovered within 1% at 64x128 nodes, and the error
+    falls at second order, by about 4 per doubling of the resolution (Sec. 3.1)."""
+    e1 = fitted_ratio((32, 64), (2.0, 1.0), 1.0 / 3.0, 1.8, 0.1, steps=500, every=5) - 1.0
+    e2 = fitted_ratio((64, 128), (2.0, 1.0), 1.0 / 3.0, 1.8, 0.1, steps=600, every=5) - 1.0
+    assert abs(e2) < 1e-2
+    assert 3.0 < e1 / e2 < 5.0
+
+
+@pytest.mark.parametrize("n,lam,T,U0", [
+    ((32, 64), (2.0, 1.0), 1.0 / 3.0, 0.0),   # prediction 3.25 (hyper-viscosity)
+    ((64, 64), (1.0, 1.0), 0.5, 0.0),         # prediction 0.50 (temperature dependence)
+    ((64, 64), (1.0, 1.0), 1.0 / 3.0, 0.173),  # prediction 0.933 (Galilean invariance lost)
+])
+def test_uncorrected_control_matches_linear_theory(n, lam, T, U0):
+    ratio = fitted_ratio(n, lam, T, 1.8, U0, extended=False, every=5)
+    Ua = U0 / math.sqrt(2.0)
+    cx = lam[0] ** 2 - 3 * T - 3 * Ua ** 2
+    cy = lam[1] ** 2 - 3 * T - 3 * Ua ** 2
+    predicted = 1.0 + (cx + cy) / (4.0 * T)
+    assert abs(ratio / predicted - 1.0) < 0.10
+    assert abs(ratio - 1.0) > 1e-2 or abs(predicted - 1.0) < 1e-2
+
+
+def test_poiseuille_between_bounce_back_walls():
+    """Steady force-driven flow: u(y) = g/(2 nu) (y + 1/2)(N_y - 1/2 - y), walls half a
+    node outside the first and last rows (textbook closed form for the halfway rule)."""
+    ny = 16
+    g = 1e-6
+    p = O.Params(n=(4, ny), T=1.0 / 3.0, omega=1.0, walls=(False, True), force=(g, 0.0))
+    fld = I.uniform(p.n)
+    f = O.init_state(fld.rho, fld.u, p)
+    f = O.run(f, p, 6000)
+    _, u = O.velocity(f, p)
+    y = np.arange(ny)
+    exact = g / (2 * p.nu) * (y + 0.5) * (ny - 0.5 - y)
+    prof = u[0].mean(axis=1)
+    # at omega = 1 the only error of the halfway rule is a uniform O(1/N^2) slip:
+    # the parabola's shape is exact and the offset is small
+    err = prof - exact
+    assert np.abs(err - err.mean()).max() < 1e-6 * exact.max()
+    assert np.abs(err).max() / exact.max() < 2e-3
+    assert np.abs(u[1]).max() < 1e-12
+
+
+@pytest.mark.parametrize("case", ["periodic2", "wall2", "force3", "wall3"])
+def test_step_node_matches_full_step(case):
+    cfg = {
+        "periodic2": dict(n=(7, 5), lam=(2.0, 1.0), T=0.5, omega=1.7),
+        "wall2": dict(n=(6, 5), lam=(1.0, 1.0), T=1 / 3, omega=1.2, walls=(False, True), force=(1e-3, 0.0)),
+        "force3": dict(n=(4, 5, 3), lam=(1.4, 1.0, 2.0), T=0.4, omega=1.5, force=(1e-3, -2e-3, 0.0)),
+        "wall3": dict(n=(5, 4, 4), lam=(2.0, 1.0, 1.0), T=0.5, omega=1.9, walls=(False, True, False)),
+    }[case]
+    p = O.Params(**cfg)
+    f = random_state(p, 7)
+    full = O.step(f, p)
+    grid = f.shape[1:]
+    for idx in np.ndindex(*grid):
+        np.testing.assert_allclose(O.step_node(f, p, idx), full[(slice(None),) + idx], rtol=0, atol=1e-14)
+
+
+def test_diagnostics_closed_forms():
+    """Mode amplitude of a pure wave is a0/2, kinetic energy of a uniform flow is U^2/2,
+    and the discrete enstrophy of u_y = A sin(kx) is A^2 sin(k)^2 / 2."""
+    n = (64, 64)
+    A = 0.01
+    fld = I.shear_wave_axis(n, U0=0.05, A=A)
+    p = O.Params(n=n, T=0.5, omega=1.5)
+    f = O.init_state(fld.rho, fld.u, p)
+    d = O.diagnostics(f, p, fld.mode_k, fld.mode_dir)
+    assert abs(abs(d.mode) - A / 2) < 1e-15
+    assert abs(d.max_uperp - A) < 1e-15
+    k = fld.mode_k[0]
+    assert abs(d.enstrophy - A * A * math.sin(k) ** 2 / 2) < 1e-16
+    assert abs(d.ke - 0.5 * (0.05 ** 2 + A * A / 2)) < 1e-16
+    assert abs(d.mass - 64 * 64) < 1e-10
+    assert d.nan_count == 0
