@@ -1,0 +1,244 @@
+/*
+ * elbm.h -- C ABI of the extended lattice Boltzmann (LBGK) step library for
+ * AMD MI355X (gfx950).
+ *
+ * The library advances lattices of populations with the LBGK equation of
+ * Saadat, Dorschner and Karlin, "Extended Lattice Boltzmann Model"
+ * (arXiv:2101.04550): pull streaming, moments, the diagonal third-moment
+ * anomaly, its central difference, the extended diagonal pressure, the
+ * product-form equilibrium and relaxation (Sec. 2.1-2.4), on the D2Q9 and
+ * D3Q27 tensor-product velocity sets with per-axis stretching (Sec. 2.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an elbm_status (0 = ELBM_OK); no C++ exception
+ *   crosses this boundary. On failure, elbm_last_error() returns a
+ *   thread-local message describing the most recent error of this thread.
+ * - Units: gas constant R = 1, time step 1 (Sec. 3). A population with
+ *   c_ia = +-1 moves one node per step; its velocity is lambda_a c_ia
+ *   (Sec. 2.2), so lambda_a is the node spacing along axis a.
+ * - Node order: cell index = x + n_x (y + n_y z) (x fastest). For D2Q9,
+ *   n_z = 1 and cell = x + n_x y.
+ * - Velocity order: i = sum_a (c_ia + 1) 3^a over the axes of the lattice,
+ *   c_ia in {-1, 0, 1}; the opposite of direction i is Q - 1 - i.
+ * - Host arrays are borrowed for the duration of the call only. Device
+ *   memory passed to elbm_create is caller-owned and borrowed until
+ *   elbm_destroy. Handles are library-owned.
+ * - One handle may be used by one thread at a time. Work is queued on the
+ *   HIP stream given at creation; calls that return host data synchronise
+ *   that stream.
+ */
+#ifndef ELBM_H
+#define ELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ELBM_ABI_VERSION 1u
+
+typedef enum elbm_status {
+  ELBM_OK = 0,
+  ELBM_EINVAL = 1,        /* a parameter is out of range or inconsistent      */
+  ELBM_EUNSUPPORTED = 2,  /* valid request this build does not implement      */
+  ELBM_ENOMEM = 3,        /* the device buffer is smaller than required       */
+  ELBM_EDEVICE = 4,       /* a HIP runtime call failed (text in last_error)   */
+  ELBM_EUNSTABLE = 5      /* diagnostics saw a non-finite value or rho <= 0   */
+} elbm_status;
+
+enum { ELBM_BC_PERIODIC = 0, ELBM_BC_BOUNCEBACK = 1 };
+
+/* Storage of the populations in device memory. The kernels always compute
+ * in FP32 on deviations h_i = f_i - w_i from the reference equilibrium
+ * w_i = f^eq_i(rho = 1, u_adv) (the lattice weights when u_adv = 0).
+ * ELBM_STORE_F32 keeps h_i in FP32; F16 and BF16 keep h_i * 2^12 (F16) or
+ * h_i (BF16), rounded to nearest even. */
+enum { ELBM_STORE_F32 = 0, ELBM_STORE_F16 = 1, ELBM_STORE_BF16 = 2 };
+
+/* Problem statement of one lattice (Sec. 2 and Sec. 3 of the paper).
+ *  abi_version  must equal ELBM_ABI_VERSION.
+ *  lattice      9 (D2Q9) or 27 (D3Q27) (Sec. 2.2, tensor-product velocity set).
+ *  n[3]         node extents along x, y, z; D2Q9 requires n[2] == 1.
+ *  lambda[3]    stretching factors lambda_a > 0 (Sec. 2.2, stretched velocities);
+ *               lambda[2] is ignored for D2Q9.
+ *  T            temperature (R = 1) (Sec. 2.1).
+ *  omega        relaxation parameter in (0, 2); kinematic viscosity
+ *               nu = (1/omega - 1/2) T (Sec. 2.1, eq. nu).
+ *  u_adv[3]     advection velocity added to the initial velocity field by
+ *               elbm_init, and reference velocity of the stored deviations.
+ *  force[3]     constant body-force acceleration g (Sec. 3.5), applied by the
+ *               exact-difference method F_i = f^eq_i(rho, u + g) - f^eq_i(rho, u).
+ *  bc[3]        per axis ELBM_BC_PERIODIC or ELBM_BC_BOUNCEBACK (halfway
+ *               bounce-back walls on both faces of that axis).
+ *  storage      ELBM_STORE_F32 / ELBM_STORE_F16 / ELBM_STORE_BF16.
+ *  extended     1: extended equilibrium (Sec. 2.3, eq. 27eqext);
+ *               0: uncorrected product-form equilibrium (Sec. 2.3, eq. 27eq).
+ *  diag_every   0: no automatic diagnostics; k > 0: elbm_step records the
+ *               diagnostics of every k-th step into a device-resident history.
+ *  diag_capacity number of history records kept (ring buffer), >= 1 when
+ *               diag_every > 0.
+ *  mode_k[3]    physical wave vector k of the measured plane mode, and
+ *  mode_dir[3]  the velocity direction d whose amplitude
+ *               < (d.u) exp(-i k.x) > the diagnostics report (Sec. 3.1).
+ */
+typedef struct elbm_params {
+  uint32_t abi_version;
+  int32_t lattice;
+  int64_t n[3];
+  double lambda[3];
+  double T;
+  double omega;
+  double u_adv[3];
+  double force[3];
+  int32_t bc[3];
+  int32_t storage;
+  int32_t extended;
+  int32_t diag_every;
+  int32_t diag_capacity;
+  int32_t reserved0;
+  double mode_k[3];
+  double mode_dir[3];
+} elbm_params;
+
+/* Global diagnostics of the post-collision state after `step` steps, reduced
+ * in FP64 (Sec. 3.1-3.3). The reported velocity is u = (j + rho g/2)/rho
+ * with j the pre-force momentum.
+ *  mass       sum over nodes of rho
+ *  mom[3]     sum over nodes of rho u
+ *  ke         (1/2) <u.u>                    (volume average, Sec. 3.2)
+ *  enstrophy  <|curl u|^2>, central differences with spacing lambda_a
+ *             (Sec. 3.3); no-slip ghost u(-1) = -u(0) on wall axes
+ *  mode_re, mode_im   <(d.u) exp(-i k.x)>, x_a = node index * lambda_a
+ *  max_uperp  max over nodes of |d.u|         (Sec. 3.1)
+ *  min_rho    minimum density
+ *  nan_count  number of nodes holding a non-finite moment */
+typedef struct elbm_diag_record {
+  int64_t step;
+  double mass;
+  double mom[3];
+  double ke;
+  double enstrophy;
+  double mode_re;
+  double mode_im;
+  double max_uperp;
+  double min_rho;
+  int64_t nan_count;
+} elbm_diag_record;
+
+typedef struct elbm_lattice* elbm_handle;
+typedef struct elbm_batch_s* elbm_batch;
+
+/* Version of the ABI this library implements (ELBM_ABI_VERSION). */
+uint32_t elbm_abi_version(void);
+
+/* Human-readable name of a status code. Never NULL; static storage. */
+const char* elbm_status_string(int32_t status);
+
+/* Thread-local text of the last error raised on this thread ("" if none). */
+const char* elbm_last_error(void);
+
+/* Checks a parameter set without touching the GPU (Sec. 2.1: omega in (0,2),
+ * T > 0; Sec. 2.2: lambda > 0, rest-population weight 1 - T/lambda^2 > 0 on
+ * every axis; at least 3 nodes on a periodic axis, 2 on a wall axis).
+ * Returns ELBM_EINVAL or ELBM_EUNSUPPORTED with a message, else ELBM_OK. */
+int32_t elbm_validate(const elbm_params* params);
+
+/* Device bytes a lattice needs: two population buffers (ping-pong) of
+ * Q * stride * sizeof(storage) bytes each plus a small fixed scratch area
+ * (descriptor, diagnostic partial sums, history). Pure host arithmetic. */
+int32_t elbm_query_bytes(const elbm_params* params, size_t* bytes);
+
+/* Creates a lattice in the caller's device buffer `dev_buf` of `bytes`
+ * bytes (>= elbm_query_bytes, 256-byte aligned; ELBM_ENOMEM if smaller) on
+ * the current HIP device. `hip_stream` (a hipStream_t, may be NULL for the
+ * null stream) is borrowed. The populations are left undefined until
+ * elbm_init or elbm_set_populations. `*out` receives the handle. */
+int32_t elbm_create(const elbm_params* params, void* dev_buf, size_t bytes,
+                    void* hip_stream, elbm_handle* out);
+
+/* Initial post-collision state f'_i(x, 0) = f^eq_i(rho, u + u_adv) with the
+ * equilibrium pressure P^eq = T + u^2 (Sec. 2.3, eq. 27eq); the step count
+ * is reset to 0 and the diagnostic history cleared.
+ *  rho  host FP64 array of N = n_x n_y n_z densities (node order above)
+ *  u    host FP64 array of D * N velocities, component-major: u[a * N + cell]
+ * Synchronises the stream before returning. */
+int32_t elbm_init(elbm_handle h, const double* rho, const double* u);
+
+/* Advances the lattice by `nsteps` >= 0 LBGK steps (Sec. 2.1, eq. LBGK):
+ * per step one fused kernel that pulls, computes moments and the anomaly,
+ * its central difference (Sec. 2.3, eq. Paastar1), the extended pressure,
+ * the product form and relaxes (plus the force). Asynchronous on the
+ * handle's stream. If diag_every > 0, diagnostics of every diag_every-th
+ * step are appended to the history. */
+int32_t elbm_step(elbm_handle h, int64_t nsteps);
+
+/* Number of steps taken since elbm_init / elbm_set_populations. */
+int64_t elbm_step_count(elbm_handle h);
+
+/* Macroscopic fields of the current state, FP64, host arrays owned by the
+ * caller: rho[N], u[D * N] (component-major), u = (j + rho g/2)/rho.
+ * Synchronises. */
+int32_t elbm_fields(elbm_handle h, double* rho, double* u);
+
+/* Populations of the current (post-collision) state as FP64 f_i = w_i + h_i:
+ * f[i * N + cell], Q * N values. Synchronises. */
+int32_t elbm_populations(elbm_handle h, double* f);
+
+/* Replaces the current state with the FP64 populations f[i * N + cell]
+ * (converted to the storage format, deviations rounded to nearest even),
+ * resets the step count and clears the history. Synchronises. */
+int32_t elbm_set_populations(elbm_handle h, const double* f);
+
+/* Computes the diagnostics of the current state now. Synchronises.
+ * Returns ELBM_EUNSTABLE (with *out filled) if a node holds a non-finite
+ * moment or rho <= 0. */
+int32_t elbm_diag(elbm_handle h, elbm_diag_record* out);
+
+/* Copies up to `max` recorded diagnostics, oldest first, into `out`;
+ * `*count` receives the number copied. Synchronises. */
+int32_t elbm_diag_history(elbm_handle h, elbm_diag_record* out, int32_t max, int32_t* count);
+
+/* Bytes of a checkpoint of this lattice (populations + step count). */
+int32_t elbm_checkpoint_bytes(elbm_handle h, size_t* bytes);
+
+/* Copies the state (raw stored populations and the step count) into the host
+ * buffer `host` of `bytes` >= elbm_checkpoint_bytes bytes. Synchronises. */
+int32_t elbm_save(elbm_handle h, void* host, size_t bytes);
+
+/* Restores a state written by elbm_save for a lattice with identical
+ * parameters; the run continues bitwise as if it had not been interrupted.
+ * ELBM_EINVAL if the checkpoint does not match. Synchronises. */
+int32_t elbm_load(elbm_handle h, const void* host, size_t bytes);
+
+/* Waits for all work queued on the handle's stream. */
+int32_t elbm_sync(elbm_handle h);
+
+/* Releases the handle (not the caller's device buffer). Synchronises. */
+int32_t elbm_destroy(elbm_handle h);
+
+/* ---- batched fused launches (many resident lattices, one launch per class) ----
+ *
+ * A batch owns a device descriptor table for up to `capacity` lattices and a
+ * cache of captured HIP graphs. elbm_batch_run advances lattice hs[k] by
+ * steps[k] >= 0 steps: every step is one launch per class of lattices
+ * (lattice, storage, walls, force) over all their tiles, whatever their
+ * sizes; lattices that have taken their steps sit out the remaining
+ * launches. Each lattice advances bitwise exactly as under elbm_step.
+ * With use_graph != 0 the launch sequence of the longest run is captured
+ * once into a HIP graph (cached by that length) and replayed; the table is
+ * uploaded before each replay. Automatic diagnostics are not recorded in a
+ * batch run. All lattices must live on the batch's device; none may appear
+ * twice. The batch allocates its own device memory (library-owned). */
+int32_t elbm_batch_create(int32_t capacity, void* hip_stream, elbm_batch* out);
+int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps,
+                       int32_t count, int32_t use_graph);
+int32_t elbm_batch_destroy(elbm_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELBM_H */

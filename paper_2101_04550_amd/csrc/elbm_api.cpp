@@ -1,0 +1,765 @@
+// C ABI of the extended-LBGK library: parameter checks, device memory layout,
+// handles, the step loop, field/population transfer, diagnostics,
+// checkpoints and the batched multi-lattice runner. See include/elbm.h.
+#include "elbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "elbm_internal.h"
+
+using namespace elbm;
+
+struct elbm_lattice {
+  elbm_params p;
+  int D = 0, Q = 0, device = 0;
+  int64_t N = 0, stride = 0;
+  size_t es = 4, pop_bytes = 0;
+  char* base = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  TableHeader* hdr_dev = nullptr;
+  LatticeDesc* desc_dev = nullptr;
+  double* partials = nullptr;
+  double* history = nullptr;
+  double* last = nullptr;
+  int64_t* hist_count = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t event = nullptr;
+  int64_t step = 0;
+  int64_t ntiles = 0;
+  bool wall = false, force = false;
+  LatticeDesc desc{};
+  LatticeConst64 c64{};
+};
+
+struct elbm_batch_s {
+  int capacity = 0, device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t copied = nullptr;
+  hipEvent_t done = nullptr;
+  bool copy_pending = false;
+  // one table per kernel class: header followed by `capacity` descriptors
+  std::map<int, char*> dev_tables;
+  char* host_stage = nullptr;  // pinned, kClasses tables
+  std::map<std::tuple<uint32_t, int64_t, std::vector<int>>, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int32_t hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return ELBM_EDEVICE;
+}
+
+#define HIPCHK(call)                                     \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+  } while (0)
+
+constexpr int kClasses = 24;  // D (2) x storage (3) x wall (2) x force (2)
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int class_of(int D, int storage, bool wall, bool force) {
+  return (((D == 3) * 3 + storage) * 2 + (wall ? 1 : 0)) * 2 + (force ? 1 : 0);
+}
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// Triplet Psi_c(u, P, lambda) (Sec. 2.2, eqs. phi0S, phiPlusS, phiMinusS).
+double psi(int c, double u, double P, double lam) {
+  if (c == 0) return 1.0 - P / (lam * lam);
+  return 0.5 * (c * u / lam + P / (lam * lam));
+}
+
+struct Layout {
+  int D = 0, Q = 0;
+  int64_t N = 0, stride = 0;
+  size_t es = 4, pop_bytes = 0;
+  size_t off_buf[2] = {0, 0};
+  size_t off_hdr = 0, off_desc = 0, off_partials = 0, off_hist = 0, off_last = 0, off_count = 0, total = 0;
+  int32_t capacity = 0;
+};
+
+int64_t stride_pad() {
+  const char* s = std::getenv("ELBM_STRIDE_PAD");
+  if (!s) return 0;
+  const long long v = std::atoll(s);
+  return v > 0 ? v : 0;
+}
+
+int32_t check(const elbm_params* p) {
+  if (!p) return fail(ELBM_EINVAL, "params is NULL");
+  if (p->abi_version != ELBM_ABI_VERSION)
+    return fail(ELBM_EINVAL, "abi_version " + std::to_string(p->abi_version) + " != " +
+                                 std::to_string(ELBM_ABI_VERSION));
+  if (p->lattice != 9 && p->lattice != 27) return fail(ELBM_EINVAL, "lattice must be 9 (D2Q9) or 27 (D3Q27)");
+  const int D = p->lattice == 27 ? 3 : 2;
+  if (D == 2 && p->n[2] != 1) return fail(ELBM_EINVAL, "D2Q9 requires n[2] == 1");
+  int64_t N = 1;
+  for (int a = 0; a < D; ++a) {
+    if (p->n[a] < 1) return fail(ELBM_EINVAL, "extents must be positive");
+    if (p->bc[a] != ELBM_BC_PERIODIC && p->bc[a] != ELBM_BC_BOUNCEBACK)
+      return fail(ELBM_EINVAL, "bc must be ELBM_BC_PERIODIC or ELBM_BC_BOUNCEBACK");
+    if (p->bc[a] == ELBM_BC_PERIODIC && p->n[a] < 3)
+      return fail(ELBM_EINVAL, "a periodic axis needs at least 3 nodes");
+    if (p->bc[a] == ELBM_BC_BOUNCEBACK && p->n[a] < 2)
+      return fail(ELBM_EINVAL, "a bounce-back axis needs at least 2 nodes");
+    if (!(p->lambda[a] > 0.0) || !std::isfinite(p->lambda[a]))
+      return fail(ELBM_EINVAL, "lambda must be positive and finite");
+    if (p->n[a] > (int64_t(1) << 30)) return fail(ELBM_EINVAL, "extent too large");
+    N *= p->n[a];
+    if (N > std::numeric_limits<int32_t>::max())
+      return fail(ELBM_EINVAL, "too many nodes: at most 2^31 - 1 per lattice");
+  }
+  if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(ELBM_EINVAL, "T must be positive and finite");
+  if (!(p->omega > 0.0 && p->omega < 2.0)) return fail(ELBM_EINVAL, "omega must lie in (0, 2)");
+  for (int a = 0; a < D; ++a) {
+    if (!(1.0 - p->T / (p->lambda[a] * p->lambda[a]) > 0.0))
+      return fail(ELBM_EINVAL, "rest weight 1 - T/lambda^2 must be positive on every axis (T < lambda_min^2)");
+  }
+  if (!finite3(p->u_adv) || !finite3(p->force) || !finite3(p->mode_k) || !finite3(p->mode_dir))
+    return fail(ELBM_EINVAL, "u_adv, force, mode_k, mode_dir must be finite");
+  if (p->storage < ELBM_STORE_F32 || p->storage > ELBM_STORE_BF16)
+    return fail(ELBM_EINVAL, "storage must be ELBM_STORE_F32, ELBM_STORE_F16 or ELBM_STORE_BF16");
+  if (p->extended != 0 && p->extended != 1) return fail(ELBM_EINVAL, "extended must be 0 or 1");
+  if (p->diag_every < 0) return fail(ELBM_EINVAL, "diag_every must be >= 0");
+  if (p->diag_every > 0 && (p->diag_capacity < 1 || p->diag_capacity > (1 << 24)))
+    return fail(ELBM_EINVAL, "diag_capacity must lie in [1, 2^24] when diag_every > 0");
+  return ELBM_OK;
+}
+
+Layout layout_of(const elbm_params* p) {
+  Layout L;
+  L.D = p->lattice == 27 ? 3 : 2;
+  L.Q = p->lattice;
+  L.N = p->n[0] * p->n[1] * p->n[2];
+  L.es = p->storage == ELBM_STORE_F32 ? 4 : 2;
+  L.stride = int64_t(align_up(size_t(L.N), 256)) + stride_pad();
+  L.pop_bytes = align_up(size_t(L.Q) * size_t(L.stride) * L.es, 4096);
+  L.capacity = p->diag_every > 0 ? p->diag_capacity : 0;
+  size_t o = 0;
+  L.off_buf[0] = o;
+  o += L.pop_bytes;
+  L.off_buf[1] = o;
+  o += L.pop_bytes;
+  L.off_hdr = o;
+  o = align_up(o + sizeof(TableHeader), kAlign);
+  L.off_desc = o;
+  o = align_up(o + sizeof(LatticeDesc), kAlign);
+  L.off_partials = o;
+  o = align_up(o + size_t(kDiagBlocks) * kRec * sizeof(double), kAlign);
+  L.off_hist = o;
+  o = align_up(o + size_t(L.capacity) * kRec * sizeof(double), kAlign);
+  L.off_last = o;
+  o = align_up(o + kRec * sizeof(double), kAlign);
+  L.off_count = o;
+  o = align_up(o + sizeof(int64_t), kAlign);
+  L.total = o;
+  return L;
+}
+
+// Marched-axis chunk: aim at about 1024 tiles (a few blocks per CU) without
+// making the ring-end overhead (2 extra planes per chunk) large.
+int choose_chunk(int D, int64_t t01, int n2) {
+  if (const char* s = std::getenv("ELBM_CHUNK")) {
+    const int v = std::atoi(s);
+    if (v > 0) return std::min(v, n2);
+  }
+  const int minc = D == 3 ? 16 : 8;
+  const int64_t want_chunks = std::max<int64_t>(1, (1024 + t01 - 1) / t01);
+  int chunk = int((n2 + want_chunks - 1) / want_chunks);
+  chunk = std::max(chunk, minc);
+  return std::min(chunk, n2);
+}
+
+void fill_desc(elbm_lattice* h) {
+  const elbm_params& p = h->p;
+  const int D = h->D;
+  LatticeDesc d{};
+  // internal axis -> physical axis (-1: absent)
+  const int phys[3] = {0, D == 3 ? 1 : -1, D == 3 ? 2 : 1};
+  for (int a = 0; a < 3; ++a) {
+    const int pa = phys[a];
+    const double lam = pa >= 0 ? p.lambda[pa] : 1.0;
+    const double ur = pa >= 0 ? p.u_adv[pa] : 0.0;
+    d.n[a] = pa >= 0 ? int32_t(p.n[pa]) : 1;
+    d.wall[a] = pa >= 0 ? (p.bc[pa] == ELBM_BC_BOUNCEBACK) : 0;
+    d.lam[a] = float(lam);
+    d.inv_lam[a] = float(1.0 / lam);
+    d.inv_lam2[a] = float(1.0 / (lam * lam));
+    d.half_inv_lam[a] = float(0.5 / lam);
+    d.anom[a] = pa >= 0 ? float(lam * lam - 3.0 * p.T) : 0.f;
+    d.uref[a] = float(ur);
+    d.g[a] = pa >= 0 ? float(p.force[pa]) : 0.f;
+    for (int c = -1; c <= 1; ++c) {
+      d.W[a][c + 1] = pa >= 0 ? float(psi(c, ur, p.T + ur * ur, lam)) : (c == 0 ? 1.f : 0.f);
+    }
+  }
+  for (int c0 = -1; c0 <= 1; ++c0)
+    for (int c1 = -1; c1 <= 1; ++c1) {
+      const double w0 = psi(c0, p.u_adv[0], p.T + p.u_adv[0] * p.u_adv[0], p.lambda[0]);
+      const double w1 = D == 3 ? psi(c1, p.u_adv[1], p.T + p.u_adv[1] * p.u_adv[1], p.lambda[1]) : (c1 == 0);
+      d.WW[c0 + 1][c1 + 1] = float(w0 * w1);
+    }
+  d.T = float(p.T);
+  d.omega = float(p.omega);
+  d.coef = p.extended ? float((2.0 - p.omega) / (2.0 * p.omega)) : 0.f;
+  const double scale = p.storage == ELBM_STORE_F16 ? double(kF16Scale) : 1.0;
+  d.scale = float(scale);
+  d.inv_scale = float(1.0 / scale);
+  d.buf[0] = h->buf[0];
+  d.buf[1] = h->buf[1];
+  d.stride = h->stride;
+  const int txw = D == 3 ? kTileX3 : 64 * kStrips2;
+  const int tyr = D == 3 ? kRows3 : 1;
+  d.tiles[0] = (d.n[0] + txw - 1) / txw;
+  d.tiles[1] = (d.n[1] + tyr - 1) / tyr;
+  d.chunk = choose_chunk(D, int64_t(d.tiles[0]) * d.tiles[1], d.n[2]);
+  d.tiles[2] = (d.n[2] + d.chunk - 1) / d.chunk;
+  d.ntiles = int64_t(d.tiles[0]) * d.tiles[1] * d.tiles[2];
+  d.tile_base = 0;
+  d.parity0 = 0;
+  d.nsteps = std::numeric_limits<int64_t>::max();
+  h->desc = d;
+  h->ntiles = d.ntiles;
+
+  LatticeConst64& c = h->c64;
+  c = LatticeConst64{};
+  c.D = D;
+  c.Q = h->Q;
+  c.N = h->N;
+  c.stride = h->stride;
+  c.storage = p.storage;
+  c.T = p.T;
+  c.scale = scale;
+  c.inv_scale = 1.0 / scale;
+  for (int a = 0; a < 3; ++a) {
+    c.n[a] = int32_t(p.n[a]);
+    const bool on = a < D;
+    c.wall[a] = on ? (p.bc[a] == ELBM_BC_BOUNCEBACK) : 0;
+    c.lam[a] = on ? p.lambda[a] : 1.0;
+    c.uref[a] = on ? p.u_adv[a] : 0.0;
+    c.g[a] = on ? p.force[a] : 0.0;
+    c.mode_k[a] = on ? p.mode_k[a] : 0.0;
+    c.mode_dir[a] = on ? p.mode_dir[a] : 0.0;
+    for (int k = -1; k <= 1; ++k)
+      c.W[a][k + 1] = on ? psi(k, c.uref[a], p.T + c.uref[a] * c.uref[a], c.lam[a]) : (k == 0 ? 1.0 : 0.0);
+  }
+  c.has_mode = (c.mode_dir[0] != 0.0 || c.mode_dir[1] != 0.0 || c.mode_dir[2] != 0.0) ? 1 : 0;
+}
+
+int grid_for_tiles(int64_t ntiles) {
+  const int64_t g = (ntiles + 7) / 8 * 8;
+  return int(std::min<int64_t>(std::max<int64_t>(g, 8), int64_t(1) << 30));
+}
+
+int32_t set_dev(int dev) {
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != dev) HIPCHK(hipSetDevice(dev));
+  return ELBM_OK;
+}
+
+void* state_buf(elbm_lattice* h) { return h->buf[h->step & 1]; }
+void* spare_buf(elbm_lattice* h) { return h->buf[(h->step & 1) ^ 1]; }
+
+int32_t reset_history(elbm_lattice* h) {
+  HIPCHK(hipMemsetAsync(h->hist_count, 0, sizeof(int64_t), h->stream));
+  return ELBM_OK;
+}
+
+int32_t run_diag(elbm_lattice* h, bool append) {
+  HIPCHK(launch_diag(h->c64, state_buf(h), static_cast<float*>(spare_buf(h)), h->partials, h->history,
+                     h->hist_count, append ? int32_t(h->p.diag_capacity) : 0, h->last, h->step, h->stream));
+  return ELBM_OK;
+}
+
+void record_to_diag(const double* r, elbm_diag_record* out) {
+  out->step = int64_t(r[R_STEP]);
+  out->mass = r[R_MASS];
+  out->mom[0] = r[R_MOM0];
+  out->mom[1] = r[R_MOM1];
+  out->mom[2] = r[R_MOM2];
+  out->ke = r[R_KE];
+  out->enstrophy = r[R_ENS];
+  out->mode_re = r[R_MODE_RE];
+  out->mode_im = r[R_MODE_IM];
+  out->max_uperp = r[R_MAXU];
+  out->min_rho = r[R_MINRHO];
+  out->nan_count = int64_t(r[R_NAN]);
+}
+
+struct CkptHeader {
+  char magic[8];
+  uint32_t abi;
+  uint32_t es;
+  int64_t step;
+  int64_t stride;
+  int64_t bytes;
+  elbm_params params;
+};
+
+bool same_problem(const elbm_params& a, const elbm_params& b) {
+  return a.lattice == b.lattice && a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2] &&
+         std::memcmp(a.lambda, b.lambda, sizeof a.lambda) == 0 && a.T == b.T && a.omega == b.omega &&
+         std::memcmp(a.u_adv, b.u_adv, sizeof a.u_adv) == 0 && std::memcmp(a.force, b.force, sizeof a.force) == 0 &&
+         std::memcmp(a.bc, b.bc, sizeof a.bc) == 0 && a.storage == b.storage && a.extended == b.extended;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t elbm_abi_version(void) { return ELBM_ABI_VERSION; }
+
+const char* elbm_status_string(int32_t s) {
+  switch (s) {
+    case ELBM_OK: return "ELBM_OK";
+    case ELBM_EINVAL: return "ELBM_EINVAL";
+    case ELBM_EUNSUPPORTED: return "ELBM_EUNSUPPORTED";
+    case ELBM_ENOMEM: return "ELBM_ENOMEM";
+    case ELBM_EDEVICE: return "ELBM_EDEVICE";
+    case ELBM_EUNSTABLE: return "ELBM_EUNSTABLE";
+    default: return "ELBM_UNKNOWN";
+  }
+}
+
+const char* elbm_last_error(void) { return g_err.c_str(); }
+
+int32_t elbm_validate(const elbm_params* p) { return check(p); }
+
+int32_t elbm_query_bytes(const elbm_params* p, size_t* bytes) {
+  if (!bytes) return fail(ELBM_EINVAL, "bytes is NULL");
+  const int32_t s = check(p);
+  if (s != ELBM_OK) return s;
+  *bytes = layout_of(p).total;
+  return ELBM_OK;
+}
+
+int32_t elbm_create(const elbm_params* p, void* dev_buf, size_t bytes, void* hip_stream, elbm_handle* out) {
+  if (!out) return fail(ELBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int32_t s = check(p);
+  if (s != ELBM_OK) return s;
+  const Layout L = layout_of(p);
+  if (!dev_buf) return fail(ELBM_EINVAL, "dev_buf is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) return fail(ELBM_EINVAL, "dev_buf must be 256-byte aligned");
+  if (bytes < L.total)
+    return fail(ELBM_ENOMEM, "device buffer holds " + std::to_string(bytes) + " bytes, " + std::to_string(L.total) +
+                                 " needed");
+  auto* h = new (std::nothrow) elbm_lattice();
+  if (!h) return fail(ELBM_EINVAL, "out of host memory");
+  h->p = *p;
+  h->D = L.D;
+  h->Q = L.Q;
+  h->N = L.N;
+  h->stride = L.stride;
+  h->es = L.es;
+  h->pop_bytes = L.pop_bytes;
+  h->base = static_cast<char*>(dev_buf);
+  h->buf[0] = h->base + L.off_buf[0];
+  h->buf[1] = h->base + L.off_buf[1];
+  h->hdr_dev = reinterpret_cast<TableHeader*>(h->base + L.off_hdr);
+  h->desc_dev = reinterpret_cast<LatticeDesc*>(h->base + L.off_desc);
+  h->partials = reinterpret_cast<double*>(h->base + L.off_partials);
+  h->history = reinterpret_cast<double*>(h->base + L.off_hist);
+  h->last = reinterpret_cast<double*>(h->base + L.off_last);
+  h->hist_count = reinterpret_cast<int64_t*>(h->base + L.off_count);
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->wall = false;
+  for (int a = 0; a < h->D; ++a) h->wall = h->wall || p->bc[a] == ELBM_BC_BOUNCEBACK;
+  h->force = p->force[0] != 0.0 || p->force[1] != 0.0 || (h->D == 3 && p->force[2] != 0.0);
+  hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->event, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "elbm_create");
+  }
+  fill_desc(h);
+  TableHeader hdr{};
+  hdr.count = 1;
+  hdr.total_tiles = h->ntiles;
+  e = hipMemcpyAsync(h->hdr_dev, &hdr, sizeof hdr, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->desc_dev, &h->desc, sizeof h->desc, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->hist_count, 0, sizeof(int64_t), h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(h->event);
+    delete h;
+    return hip_fail(e, "elbm_create upload");
+  }
+  *out = h;
+  return ELBM_OK;
+}
+
+int32_t elbm_init(elbm_handle h, const double* rho, const double* u) {
+  if (!h || !rho || !u) return fail(ELBM_EINVAL, "NULL argument");
+  int32_t s = set_dev(h->device);
+  if (s) return s;
+  h->step = 0;
+  const int D = h->D;
+  const int64_t per = int64_t(h->pop_bytes / (size_t(D + 1) * sizeof(double)));
+  double* stage = static_cast<double*>(h->buf[1]);
+  for (int64_t c0 = 0; c0 < h->N; c0 += per) {
+    const int64_t cnt = std::min(per, h->N - c0);
+    HIPCHK(hipMemcpyAsync(stage, rho + c0, cnt * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    for (int a = 0; a < D; ++a)
+      HIPCHK(hipMemcpyAsync(stage + (1 + a) * cnt, u + a * h->N + c0, cnt * sizeof(double), hipMemcpyHostToDevice,
+                            h->stream));
+    HIPCHK(launch_init(h->c64, stage, c0, cnt, h->buf[0], h->stream));
+  }
+  s = reset_history(h);
+  if (s) return s;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ELBM_OK;
+}
+
+int32_t elbm_step(elbm_handle h, int64_t nsteps) {
+  if (!h) return fail(ELBM_EINVAL, "NULL handle");
+  if (nsteps < 0) return fail(ELBM_EINVAL, "nsteps must be >= 0");
+  int32_t s = set_dev(h->device);
+  if (s) return s;
+  const int grid = grid_for_tiles(h->ntiles);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    HIPCHK(launch_step(h->D, h->p.storage, h->wall, h->force, h->hdr_dev, h->desc_dev, h->step, grid, h->stream));
+    ++h->step;
+    if (h->p.diag_every > 0 && h->step % h->p.diag_every == 0) {
+      s = run_diag(h, true);
+      if (s) return s;
+    }
+  }
+  return ELBM_OK;
+}
+
+int64_t elbm_step_count(elbm_handle h) { return h ? h->step : -1; }
+
+int32_t elbm_fields(elbm_handle h, double* rho, double* u) {
+  if (!h || !rho || !u) return fail(ELBM_EINVAL, "NULL argument");
+  int32_t s = set_dev(h->device);
+  if (s) return s;
+  double* stage = static_cast<double*>(spare_buf(h));
+  for (int comp = 0; comp <= h->D; ++comp) {
+    HIPCHK(launch_field(h->c64, state_buf(h), comp, stage, h->stream));
+    double* dst = comp == 0 ? rho : u + int64_t(comp - 1) * h->N;
+    HIPCHK(hipMemcpyAsync(dst, stage, h->N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  return ELBM_OK;
+}
+
+int32_t elbm_populations(elbm_handle h, double* f) {
+  if (!h || !f) return fail(ELBM_EINVAL, "NULL argument");
+  int32_t s = set_dev(h->device);
+  if (s) return s;
+  double* stage = static_cast<double*>(spare_buf(h));
+  for (int i = 0; i < h->Q; ++i) {
+    HIPCHK(launch_pop_out(h->c64, state_buf(h), i, stage, h->stream));
+    HIPCHK(hipMemcpyAsync(f + int64_t(i) * h->N, stage, h->N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  return ELBM_OK;
+}
+
+int32_t elbm_set_populations(elbm_handle h, const double* f) {
+  if (!h || !f) return fail(ELBM_EINVAL, "NULL argument");
+  int32_t s = set_dev(h->device);
+  if (s) return s;
+  h->step = 0;
+  double* stage = static_cast<double*>(h->buf[1]);
+  for (int i = 0; i < h->Q; ++i) {
+    HIPCHK(hipMemcpyAsync(stage, f + int64_t(i) * h->N, h->N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(launch_pop_in(h->c64, stage, i, h->buf[0], h->stream));
+  }
+  s = reset_history(h);
+  if (s) return s;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ELBM_OK;
+}
+
+int32_t elbm_diag(elbm_handle h, elbm_diag_record* out) {
+  if (!h || !out) return fail(ELBM_EINVAL, "NULL argument");
+  int32_t s = set_dev(h->device);
+  if (s) return s;
+  s = run_diag(h, false);
+  if (s) return s;
+  double rec[kRec];
+  HIPCHK(hipMemcpyAsync(rec, h->last, sizeof rec, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  record_to_diag(rec, out);
+  if (out->nan_count > 0 || !(out->min_rho > 0.0))
+    return fail(ELBM_EUNSTABLE, "non-finite moment or non-positive density at step " + std::to_string(h->step));
+  return ELBM_OK;
+}
+
+int32_t elbm_diag_history(elbm_handle h, elbm_diag_record* out, int32_t max, int32_t* count) {
+  if (!h || !count || (max > 0 && !out)) return fail(ELBM_EINVAL, "NULL argument");
+  *count = 0;
+  const int32_t cap = h->p.diag_every > 0 ? h->p.diag_capacity : 0;
+  if (cap == 0 || max <= 0) return ELBM_OK;
+  int32_t s = set_dev(h->device);
+  if (s) return s;
+  int64_t n = 0;
+  std::vector<double> ring(size_t(cap) * kRec);
+  HIPCHK(hipMemcpyAsync(&n, h->hist_count, sizeof n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(ring.data(), h->history, ring.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const int64_t kept = std::min<int64_t>(n, cap);
+  const int64_t first = n - kept;
+  const int64_t take = std::min<int64_t>(kept, max);
+  for (int64_t r = 0; r < take; ++r) record_to_diag(&ring[size_t((first + r) % cap) * kRec], &out[r]);
+  *count = int32_t(take);
+  return ELBM_OK;
+}
+
+int32_t elbm_checkpoint_bytes(elbm_handle h, size_t* bytes) {
+  if (!h || !bytes) return fail(ELBM_EINVAL, "NULL argument");
+  *bytes = sizeof(CkptHeader) + size_t(h->Q) * size_t(h->stride) * h->es;
+  return ELBM_OK;
+}
+
+int32_t elbm_save(elbm_handle h, void* host, size_t bytes) {
+  if (!h || !host) return fail(ELBM_EINVAL, "NULL argument");
+  size_t need = 0;
+  elbm_checkpoint_bytes(h, &need);
+  if (bytes < need) return fail(ELBM_EINVAL, "checkpoint buffer too small");
+  int32_t s = set_dev(h->device);
+  if (s) return s;
+  CkptHeader hd{};
+  std::memcpy(hd.magic, "ELBMCKP1", 8);
+  hd.abi = ELBM_ABI_VERSION;
+  hd.es = uint32_t(h->es);
+  hd.step = h->step;
+  hd.stride = h->stride;
+  hd.bytes = int64_t(need);
+  hd.params = h->p;
+  std::memcpy(host, &hd, sizeof hd);
+  HIPCHK(hipMemcpyAsync(static_cast<char*>(host) + sizeof hd, state_buf(h), need - sizeof hd, hipMemcpyDeviceToHost,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ELBM_OK;
+}
+
+int32_t elbm_load(elbm_handle h, const void* host, size_t bytes) {
+  if (!h || !host) return fail(ELBM_EINVAL, "NULL argument");
+  size_t need = 0;
+  elbm_checkpoint_bytes(h, &need);
+  if (bytes < need) return fail(ELBM_EINVAL, "checkpoint buffer too small");
+  CkptHeader hd;
+  std::memcpy(&hd, host, sizeof hd);
+  if (std::memcmp(hd.magic, "ELBMCKP1", 8) != 0 || hd.abi != ELBM_ABI_VERSION || hd.es != h->es ||
+      hd.stride != h->stride || hd.bytes != int64_t(need) || !same_problem(hd.params, h->p) || hd.step < 0)
+    return fail(ELBM_EINVAL, "checkpoint does not match this lattice");
+  int32_t s = set_dev(h->device);
+  if (s) return s;
+  h->step = hd.step;
+  HIPCHK(hipMemcpyAsync(state_buf(h), static_cast<const char*>(host) + sizeof hd, need - sizeof hd,
+                        hipMemcpyHostToDevice, h->stream));
+  s = reset_history(h);
+  if (s) return s;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ELBM_OK;
+}
+
+int32_t elbm_sync(elbm_handle h) {
+  if (!h) return fail(ELBM_EINVAL, "NULL handle");
+  int32_t s = set_dev(h->device);
+  if (s) return s;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ELBM_OK;
+}
+
+int32_t elbm_destroy(elbm_handle h) {
+  if (!h) return ELBM_OK;
+  set_dev(h->device);
+  hipError_t e = hipStreamSynchronize(h->stream);
+  (void)hipEventDestroy(h->event);
+  delete h;
+  if (e != hipSuccess) return hip_fail(e, "elbm_destroy");
+  return ELBM_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+int32_t elbm_batch_create(int32_t capacity, void* hip_stream, elbm_batch* out) {
+  if (!out) return fail(ELBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (capacity < 1 || capacity > 65536) return fail(ELBM_EINVAL, "capacity must lie in [1, 65536]");
+  auto* b = new (std::nothrow) elbm_batch_s();
+  if (!b) return fail(ELBM_EINVAL, "out of host memory");
+  b->capacity = capacity;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  const size_t tbytes = align_up(sizeof(TableHeader), 64) + size_t(capacity) * sizeof(LatticeDesc);
+  hipError_t e = hipGetDevice(&b->device);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->host_stage), tbytes * kClasses);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (b->host_stage) (void)hipHostFree(b->host_stage);
+    delete b;
+    return hip_fail(e, "elbm_batch_create");
+  }
+  *out = b;
+  return ELBM_OK;
+}
+
+int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps, int32_t count, int32_t use_graph) {
+  if (!b) return fail(ELBM_EINVAL, "NULL batch");
+  if (count < 0 || count > b->capacity) return fail(ELBM_EINVAL, "count exceeds the batch capacity");
+  if (count > 0 && (!hs || !steps)) return fail(ELBM_EINVAL, "NULL argument");
+  for (int32_t k = 0; k < count; ++k) {
+    if (!hs[k]) return fail(ELBM_EINVAL, "NULL handle in batch");
+    if (steps[k] < 0) return fail(ELBM_EINVAL, "steps must be >= 0");
+    if (hs[k]->device != b->device) return fail(ELBM_EINVAL, "lattice on another device");
+    for (int32_t m = 0; m < k; ++m)
+      if (hs[m] == hs[k]) return fail(ELBM_EINVAL, "a lattice appears twice in the batch");
+  }
+  int32_t s = set_dev(b->device);
+  if (s) return s;
+  int64_t smax = 0;
+  for (int32_t k = 0; k < count; ++k) smax = std::max(smax, steps[k]);
+  if (smax == 0) return ELBM_OK;
+
+  const size_t hbytes = align_up(sizeof(TableHeader), 64);
+  const size_t tbytes = hbytes + size_t(b->capacity) * sizeof(LatticeDesc);
+  // the pinned staging must not change while the previous upload is pending
+  if (b->copy_pending) HIPCHK(hipEventSynchronize(b->copied));
+
+  // group by kernel class; within a class keep the caller's order
+  std::vector<std::vector<int32_t>> members(kClasses);
+  for (int32_t k = 0; k < count; ++k) {
+    if (steps[k] == 0) continue;
+    const elbm_lattice* h = hs[k];
+    members[class_of(h->D, h->p.storage, h->wall, h->force)].push_back(k);
+  }
+  uint32_t mask = 0;
+  std::vector<int> grids;
+  for (int c = 0; c < kClasses; ++c) {
+    if (members[c].empty()) continue;
+    mask |= 1u << c;
+    char* hostt = b->host_stage + size_t(c) * tbytes;
+    auto* hdr = reinterpret_cast<TableHeader*>(hostt);
+    auto* tab = reinterpret_cast<LatticeDesc*>(hostt + hbytes);
+    int64_t base = 0;
+    int n = 0;
+    for (int32_t k : members[c]) {
+      LatticeDesc d = hs[k]->desc;
+      d.tile_base = base;
+      d.parity0 = int32_t(hs[k]->step & 1);
+      d.nsteps = steps[k];
+      base += d.ntiles;
+      tab[n++] = d;
+    }
+    hdr->count = n;
+    hdr->pad = 0;
+    hdr->total_tiles = base;
+    if (!b->dev_tables.count(c)) {
+      char* p = nullptr;
+      HIPCHK(hipMalloc(reinterpret_cast<void**>(&p), tbytes));
+      b->dev_tables[c] = p;
+    }
+    // persistent grid: a power of two >= the tiles (capped), so that one
+    // captured graph serves every mix of the same size class
+    int64_t g = 64;
+    while (g < base && g < 4096) g *= 2;
+    grids.push_back(int(g));
+  }
+  // order the device work after what is pending on the lattices' streams
+  for (int32_t k = 0; k < count; ++k) {
+    HIPCHK(hipEventRecord(hs[k]->event, hs[k]->stream));
+    HIPCHK(hipStreamWaitEvent(b->stream, hs[k]->event, 0));
+  }
+  for (int c = 0; c < kClasses; ++c) {
+    if (!(mask & (1u << c))) continue;
+    const size_t n = hbytes + size_t(members[c].size()) * sizeof(LatticeDesc);
+    HIPCHK(hipMemcpyAsync(b->dev_tables[c], b->host_stage + size_t(c) * tbytes, n, hipMemcpyHostToDevice, b->stream));
+  }
+  HIPCHK(hipEventRecord(b->copied, b->stream));
+  b->copy_pending = true;
+
+  auto launch_all = [&](hipStream_t st) -> int32_t {
+    for (int64_t sub = 0; sub < smax; ++sub) {
+      int gi = 0;
+      for (int c = 0; c < kClasses; ++c) {
+        if (!(mask & (1u << c))) continue;
+        const int D = c >= 12 ? 3 : 2;
+        const int storage = (c / 4) % 3;
+        const bool wall = (c / 2) % 2;
+        const bool force = c % 2;
+        const auto* hdr = reinterpret_cast<const TableHeader*>(b->dev_tables[c]);
+        const auto* tab = reinterpret_cast<const LatticeDesc*>(b->dev_tables[c] + hbytes);
+        HIPCHK(launch_step(D, storage, wall, force, hdr, tab, sub, grids[gi++], st));
+      }
+    }
+    return ELBM_OK;
+  };
+
+  if (use_graph) {
+    auto key = std::make_tuple(mask, smax, grids);
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+      HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      const int32_t ls = launch_all(b->stream);
+      hipGraph_t graph = nullptr;
+      const hipError_t ee = hipStreamEndCapture(b->stream, &graph);
+      if (ls != ELBM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return ls;
+      }
+      if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
+      if (b->graphs.size() >= 64) {
+        (void)hipGraphExecDestroy(b->graphs.begin()->second);
+        b->graphs.erase(b->graphs.begin());
+      }
+      it = b->graphs.emplace(key, exec).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, b->stream));
+  } else {
+    s = launch_all(b->stream);
+    if (s) return s;
+  }
+  HIPCHK(hipEventRecord(b->done, b->stream));
+  for (int32_t k = 0; k < count; ++k) {
+    hs[k]->step += steps[k];
+    HIPCHK(hipStreamWaitEvent(hs[k]->stream, b->done, 0));
+  }
+  return ELBM_OK;
+}
+
+int32_t elbm_batch_destroy(elbm_batch b) {
+  if (!b) return ELBM_OK;
+  set_dev(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : b->dev_tables) (void)hipFree(kv.second);
+  if (b->host_stage) (void)hipHostFree(b->host_stage);
+  (void)hipEventDestroy(b->copied);
+  (void)hipEventDestroy(b->done);
+  delete b;
+  return ELBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,368 @@
+// Non-hot kernels: initial state, population conversion, macroscopic fields
+// and the FP64 global diagnostics.
+//
+// All of them work on the stored deviations h_i = f_i - w_i with
+// w_i = prod_a W_a[c_ia] the reference equilibrium of the lattice, and use
+// FP64 arithmetic. Node order is x fastest; velocity index
+// i = sum_a (c_ia + 1) 3^a over the physical axes.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "elbm_internal.h"
+
+namespace elbm {
+namespace {
+
+template <int S>
+struct Raw;
+template <>
+struct Raw<0> {
+  using T = float;
+  __device__ static double get(const T* p) { return double(*p); }
+  __device__ static void put(T* p, double v) { *p = float(v); }
+};
+// FP64 -> FP32 with round-to-odd: a following round-to-nearest-even to a
+// format with at least two fewer significand bits then rounds the FP64 value
+// correctly (no double rounding).
+__device__ __forceinline__ float to_f32_odd(double v) {
+  float f = float(v);
+  const double back = double(f);
+  if (back != v) {
+    unsigned int b = __float_as_uint(f);
+    if ((b & 1u) == 0u) b += fabs(v) > fabs(back) ? 1u : 0xFFFFFFFFu;
+    f = __uint_as_float(b);
+  }
+  return f;
+}
+
+template <>
+struct Raw<1> {
+  using T = __half;
+  __device__ static double get(const T* p) { return double(__half2float(*p)); }
+  __device__ static void put(T* p, double v) { *p = __float2half_rn(to_f32_odd(v)); }
+};
+template <>
+struct Raw<2> {
+  using T = __hip_bfloat16;
+  __device__ static double get(const T* p) { return double(__bfloat162float(*p)); }
+  __device__ static void put(T* p, double v) { *p = __float2bfloat16(to_f32_odd(v)); }
+};
+
+__device__ __forceinline__ int cdir(int i, int a) {
+  int r = i;
+  for (int k = 0; k < a; ++k) r /= 3;
+  return r % 3 - 1;
+}
+
+// Reference weight w_i = prod_a W_a[c_ia] in FP64.
+__device__ __forceinline__ double ref_weight(const LatticeConst64& c, int i) {
+  double w = 1.0;
+  for (int a = 0; a < c.D; ++a) w *= c.W[a][cdir(i, a) + 1];
+  return w;
+}
+
+// Triplet Psi_c(u, P, lambda) (Sec. 2.2, eqs. phi0S, phiPlusS, phiMinusS).
+__device__ __forceinline__ double psi(int ci, double u, double P, double lam) {
+  if (ci == 0) return 1.0 - P / (lam * lam);
+  return 0.5 * (ci * u / lam + P / (lam * lam));
+}
+
+template <int S>
+__global__ void init_kernel(LatticeConst64 c, const double* __restrict__ stage, int64_t cell0, int64_t count,
+                            void* __restrict__ dstv) {
+  using T = typename Raw<S>::T;
+  T* dst = static_cast<T*>(dstv);
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < count;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const double rho = stage[k];
+    double u[3], P[3];
+    for (int a = 0; a < c.D; ++a) {
+      u[a] = stage[(1 + a) * count + k] + c.uref[a];
+      P[a] = c.T + u[a] * u[a];  // equilibrium pressure (Sec. 2.3, eq. Peqa)
+    }
+    const int64_t cell = cell0 + k;
+    for (int i = 0; i < c.Q; ++i) {
+      double f = rho, w = 1.0;
+      for (int a = 0; a < c.D; ++a) {
+        const int ci = cdir(i, a);
+        f *= psi(ci, u[a], P[a], c.lam[a]);
+        w *= c.W[a][ci + 1];
+      }
+      Raw<S>::put(dst + i * c.stride + cell, (f - w) * c.scale);
+    }
+  }
+}
+
+template <int S>
+__global__ void pop_out_kernel(LatticeConst64 c, const void* __restrict__ srcv, int i, double* __restrict__ out) {
+  using T = typename Raw<S>::T;
+  const T* src = static_cast<const T*>(srcv) + i * c.stride;
+  const double w = ref_weight(c, i);
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < c.N; k += int64_t(gridDim.x) * blockDim.x)
+    out[k] = w + Raw<S>::get(src + k) * c.inv_scale;
+}
+
+template <int S>
+__global__ void pop_in_kernel(LatticeConst64 c, const double* __restrict__ in, int i, void* __restrict__ dstv) {
+  using T = typename Raw<S>::T;
+  T* dst = static_cast<T*>(dstv) + i * c.stride;
+  const double w = ref_weight(c, i);
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < c.N; k += int64_t(gridDim.x) * blockDim.x)
+    Raw<S>::put(dst + k, (in[k] - w) * c.scale);
+}
+
+// FP64 moments of one node of the stored state: rho and the reported
+// velocity u = j/rho - g/2 (j the stored, post-force momentum).
+template <int S>
+__device__ __forceinline__ void node_moments(const LatticeConst64& c, const typename Raw<S>::T* src, int64_t cell,
+                                             double& rho, double (&u)[3]) {
+  double dr = 0.0, dj[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < c.Q; ++i) {
+    const double h = Raw<S>::get(src + i * c.stride + cell) * c.inv_scale;
+    dr += h;
+    for (int a = 0; a < c.D; ++a) dj[a] += cdir(i, a) * h;
+  }
+  rho = 1.0 + dr;
+  for (int a = 0; a < 3; ++a) {
+    u[a] = 0.0;
+    if (a < c.D) u[a] = (c.uref[a] + c.lam[a] * dj[a]) / rho - 0.5 * c.g[a];
+  }
+}
+
+template <int S>
+__global__ void field_kernel(LatticeConst64 c, const void* __restrict__ srcv, int comp, double* __restrict__ out) {
+  using T = typename Raw<S>::T;
+  const T* src = static_cast<const T*>(srcv);
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < c.N; k += int64_t(gridDim.x) * blockDim.x) {
+    double rho, u[3];
+    node_moments<S>(c, src, k, rho, u);
+    out[k] = comp == 0 ? rho : u[comp - 1];
+  }
+}
+
+// ---- deterministic FP64 block reductions ----
+constexpr int kDiagThreads = 256;
+
+struct Acc {
+  double v[kRec];
+};
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+// Reduces field f of every thread of the block (fixed order) into lane 0 of
+// thread 0; kind 0 sum, 1 max, 2 min.
+__device__ double block_reduce(double x, int kind, double* sh) {
+  x = kind == 0 ? wave_sum(x) : (kind == 1 ? wave_max(x) : wave_min(x));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = x;
+  __syncthreads();
+  double r = sh[0];
+  for (int k = 1; k < kDiagThreads / 64; ++k)
+    r = kind == 0 ? r + sh[k] : (kind == 1 ? fmax(r, sh[k]) : fmin(r, sh[k]));
+  return r;
+}
+
+__device__ __forceinline__ int field_kind(int f) { return f == R_MAXU ? 1 : (f == R_MINRHO ? 2 : 0); }
+
+template <int S>
+__global__ void __launch_bounds__(kDiagThreads)
+    diag_moments_kernel(LatticeConst64 c, const void* __restrict__ srcv, float* __restrict__ ustage,
+                        double* __restrict__ partials) {
+  using T = typename Raw<S>::T;
+  const T* src = static_cast<const T*>(srcv);
+  __shared__ double sh[kDiagThreads / 64];
+  double acc[kRec];
+  for (int f = 0; f < kRec; ++f) acc[f] = 0.0;
+  acc[R_MAXU] = 0.0;
+  acc[R_MINRHO] = 1e300;
+  const int nx = c.n[0], ny = c.n[1];
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < c.N; k += int64_t(gridDim.x) * blockDim.x) {
+    double rho, u[3];
+    node_moments<S>(c, src, k, rho, u);
+    const bool finite = isfinite(rho) && isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]);
+    acc[R_NAN] += finite ? 0.0 : 1.0;
+    acc[R_MASS] += rho;
+    acc[R_MOM0] += rho * u[0];
+    acc[R_MOM1] += rho * u[1];
+    acc[R_MOM2] += rho * u[2];
+    acc[R_KE] += u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    acc[R_MINRHO] = fmin(acc[R_MINRHO], finite ? rho : -1e300);
+    for (int a = 0; a < 3; ++a) ustage[a * c.N + k] = float(u[a]);
+    if (c.has_mode) {
+      const int64_t x = k % nx, y = (k / nx) % ny, z = k / (int64_t(nx) * ny);
+      const double ph = c.mode_k[0] * (x * c.lam[0]) + c.mode_k[1] * (y * c.lam[1]) + c.mode_k[2] * (z * c.lam[2]);
+      const double up = c.mode_dir[0] * u[0] + c.mode_dir[1] * u[1] + c.mode_dir[2] * u[2];
+      double sn, cs;
+      sincos(ph, &sn, &cs);
+      acc[R_MODE_RE] += up * cs;
+      acc[R_MODE_IM] -= up * sn;
+      acc[R_MAXU] = fmax(acc[R_MAXU], fabs(up));
+    }
+  }
+  for (int f = 1; f < R_USED; ++f) {
+    if (f == R_ENS) continue;
+    const double r = block_reduce(acc[f], field_kind(f), sh);
+    if (threadIdx.x == 0) partials[blockIdx.x * kRec + f] = r;
+  }
+}
+
+// Central difference of velocity component comp along axis b at node (x,y,z),
+// spacing lambda_b; periodic wrap, or the no-slip ghost u(-1) = -u(0) on a
+// wall axis.
+__device__ __forceinline__ double dudx(const LatticeConst64& c, const float* u, int comp, int b, int x, int y, int z) {
+  const int n = c.n[b];
+  const int p[3] = {x, y, z};
+  const int64_t own = x + int64_t(c.n[0]) * (y + int64_t(c.n[1]) * z);
+  const double uo = u[comp * c.N + own];
+  const int64_t st = b == 0 ? 1 : (b == 1 ? c.n[0] : int64_t(c.n[0]) * c.n[1]);
+  double up, um;
+  if (p[b] + 1 < n) up = u[comp * c.N + own + st];
+  else up = c.wall[b] ? -uo : u[comp * c.N + own - (n - 1) * st];
+  if (p[b] > 0) um = u[comp * c.N + own - st];
+  else um = c.wall[b] ? -uo : u[comp * c.N + own + (n - 1) * st];
+  return (up - um) / (2.0 * c.lam[b]);
+}
+
+__global__ void __launch_bounds__(kDiagThreads)
+    diag_curl_kernel(LatticeConst64 c, const float* __restrict__ ustage, double* __restrict__ partials) {
+  __shared__ double sh[kDiagThreads / 64];
+  double ens = 0.0;
+  const int nx = c.n[0], ny = c.n[1];
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < c.N; k += int64_t(gridDim.x) * blockDim.x) {
+    const int x = int(k % nx), y = int((k / nx) % ny), z = int(k / (int64_t(nx) * ny));
+    if (c.D == 2) {
+      const double wz = dudx(c, ustage, 1, 0, x, y, z) - dudx(c, ustage, 0, 1, x, y, z);
+      ens += wz * wz;
+    } else {
+      const double wx = dudx(c, ustage, 2, 1, x, y, z) - dudx(c, ustage, 1, 2, x, y, z);
+      const double wy = dudx(c, ustage, 0, 2, x, y, z) - dudx(c, ustage, 2, 0, x, y, z);
+      const double wz = dudx(c, ustage, 1, 0, x, y, z) - dudx(c, ustage, 0, 1, x, y, z);
+      ens += wx * wx + wy * wy + wz * wz;
+    }
+  }
+  const double r = block_reduce(ens, 0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x * kRec + R_ENS] = r;
+}
+
+// One block: fixed-order reduction of the per-block partials into a record.
+// The record goes to history[(*count) % capacity] and *count is incremented
+// when capacity > 0; it always goes to `last` (the record after the ring).
+__global__ void __launch_bounds__(kDiagThreads)
+    diag_final_kernel(const double* __restrict__ partials, int nblocks, double* __restrict__ history,
+                      int64_t* __restrict__ count, int32_t capacity, double* __restrict__ last, int64_t step,
+                      double ncells) {
+  __shared__ double sh[kDiagThreads / 64];
+  double rec[kRec];
+  for (int f = 0; f < kRec; ++f) {
+    const int kind = field_kind(f);
+    double x = kind == 0 ? 0.0 : (kind == 1 ? 0.0 : 1e300);
+    for (int b = threadIdx.x; b < nblocks; b += kDiagThreads) {
+      const double v = partials[b * kRec + f];
+      x = kind == 0 ? x + v : (kind == 1 ? fmax(x, v) : fmin(x, v));
+    }
+    rec[f] = block_reduce(x, kind, sh);
+  }
+  if (threadIdx.x == 0) {
+    rec[R_STEP] = double(step);
+    rec[R_KE] = 0.5 * rec[R_KE] / ncells;
+    rec[R_ENS] = rec[R_ENS] / ncells;
+    rec[R_MODE_RE] /= ncells;
+    rec[R_MODE_IM] /= ncells;
+    for (int f = R_USED; f < kRec; ++f) rec[f] = 0.0;
+    for (int f = 0; f < kRec; ++f) last[f] = rec[f];
+    if (capacity > 0) {
+      const int64_t n = *count;
+      double* dst = history + (n % capacity) * kRec;
+      for (int f = 0; f < kRec; ++f) dst[f] = rec[f];
+      *count = n + 1;
+    }
+  }
+}
+
+int grid_for(int64_t n, int threads) {
+  const int64_t g = (n + threads - 1) / threads;
+  return int(g < 4096 ? (g > 0 ? g : 1) : 4096);
+}
+
+}  // namespace
+
+hipError_t launch_init(const LatticeConst64& c, const double* stage, int64_t cell0, int64_t count, void* dst,
+                       hipStream_t st) {
+  const int g = grid_for(count, 256);
+  switch (c.storage) {
+    case 0: hipLaunchKernelGGL(init_kernel<0>, dim3(g), dim3(256), 0, st, c, stage, cell0, count, dst); break;
+    case 1: hipLaunchKernelGGL(init_kernel<1>, dim3(g), dim3(256), 0, st, c, stage, cell0, count, dst); break;
+    case 2: hipLaunchKernelGGL(init_kernel<2>, dim3(g), dim3(256), 0, st, c, stage, cell0, count, dst); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pop_out(const LatticeConst64& c, const void* src, int i, double* out, hipStream_t st) {
+  const int g = grid_for(c.N, 256);
+  switch (c.storage) {
+    case 0: hipLaunchKernelGGL(pop_out_kernel<0>, dim3(g), dim3(256), 0, st, c, src, i, out); break;
+    case 1: hipLaunchKernelGGL(pop_out_kernel<1>, dim3(g), dim3(256), 0, st, c, src, i, out); break;
+    case 2: hipLaunchKernelGGL(pop_out_kernel<2>, dim3(g), dim3(256), 0, st, c, src, i, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pop_in(const LatticeConst64& c, const double* in, int i, void* dst, hipStream_t st) {
+  const int g = grid_for(c.N, 256);
+  switch (c.storage) {
+    case 0: hipLaunchKernelGGL(pop_in_kernel<0>, dim3(g), dim3(256), 0, st, c, in, i, dst); break;
+    case 1: hipLaunchKernelGGL(pop_in_kernel<1>, dim3(g), dim3(256), 0, st, c, in, i, dst); break;
+    case 2: hipLaunchKernelGGL(pop_in_kernel<2>, dim3(g), dim3(256), 0, st, c, in, i, dst); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_field(const LatticeConst64& c, const void* src, int comp, double* out, hipStream_t st) {
+  const int g = grid_for(c.N, 256);
+  switch (c.storage) {
+    case 0: hipLaunchKernelGGL(field_kernel<0>, dim3(g), dim3(256), 0, st, c, src, comp, out); break;
+    case 1: hipLaunchKernelGGL(field_kernel<1>, dim3(g), dim3(256), 0, st, c, src, comp, out); break;
+    case 2: hipLaunchKernelGGL(field_kernel<2>, dim3(g), dim3(256), 0, st, c, src, comp, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(const LatticeConst64& c, const void* src, float* ustage, double* partials, double* history,
+                       int64_t* hist_count, int32_t capacity, double* last, int64_t step, hipStream_t st) {
+  const int nb = kDiagBlocks;
+  switch (c.storage) {
+    case 0: hipLaunchKernelGGL(diag_moments_kernel<0>, dim3(nb), dim3(kDiagThreads), 0, st, c, src, ustage, partials); break;
+    case 1: hipLaunchKernelGGL(diag_moments_kernel<1>, dim3(nb), dim3(kDiagThreads), 0, st, c, src, ustage, partials); break;
+    case 2: hipLaunchKernelGGL(diag_moments_kernel<2>, dim3(nb), dim3(kDiagThreads), 0, st, c, src, ustage, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_curl_kernel, dim3(nb), dim3(kDiagThreads), 0, st, c, ustage, partials);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kDiagThreads), 0, st, partials, nb, history, hist_count,
+                     capacity, last, step, double(c.N));
+  return hipGetLastError();
+}
+
+}  // namespace elbm

@@ -1,0 +1,106 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code.
+//
+// Axis roles inside the kernels. A lattice is stored as Q structure-of-arrays
+// population arrays, x fastest. The kernels see three internal axes:
+//   axis 0 -- x, the fastest (coalesced) axis, tiled in 64-wide wavefronts;
+//   axis 1 -- the tiled row axis (y for D3Q27; absent, extent 1, for D2Q9);
+//   axis 2 -- the marched axis, walked plane by plane with a register ring
+//             (z for D3Q27; y for D2Q9).
+// So a D2Q9 lattice n_x x n_y is handled as internal extents (n_x, 1, n_y)
+// with velocity components (c_x, 0, c_y); memory order is unchanged.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace elbm {
+
+constexpr int kTileX3 = 64;        // x width of a D3Q27 tile: one wavefront
+constexpr int kRows3 = 8;          // y rows of a D3Q27 tile -> 512 threads
+constexpr int kStrips2 = 4;        // 64-wide strips of a D2Q9 tile -> 256 threads
+constexpr int kDiagBlocks = 512;   // fixed grid of the diagnostic reductions
+constexpr int kRec = 16;           // doubles per diagnostic record / partial
+constexpr float kF16Scale = 4096.0f;
+
+// Record layout (doubles) of a diagnostic partial or history entry.
+enum RecField {
+  R_STEP = 0, R_MASS, R_MOM0, R_MOM1, R_MOM2, R_KE, R_ENS, R_MODE_RE, R_MODE_IM,
+  R_MAXU, R_MINRHO, R_NAN, R_USED
+};
+
+// One entry of the device descriptor table: everything a block needs to
+// advance one tile of one lattice. Plain data, copied host -> device.
+struct alignas(16) LatticeDesc {
+  void* buf[2];            // population buffers; state of substep s is in buf[(parity0 + s) & 1]
+  int64_t stride;          // elements between consecutive population arrays
+  int64_t tile_base;       // first global tile index of this lattice in its table
+  int64_t ntiles;          // tiles of this lattice
+  int64_t nsteps;          // substeps this lattice takes part in (s < nsteps)
+  int32_t n[3];            // internal extents (see axis roles above)
+  int32_t tiles[3];        // tile counts along the internal axes
+  int32_t chunk;           // marched planes per tile
+  int32_t parity0;
+  int32_t wall[3];         // internal axis has halfway bounce-back walls
+  int32_t pad0;
+  float lam[3];            // stretching per internal axis (1 on an absent axis)
+  float inv_lam[3];
+  float inv_lam2[3];
+  float half_inv_lam[3];   // 1 / (2 lambda): central-difference factor
+  float anom[3];           // lambda^2 - 3T: linear coefficient of the anomaly
+  float uref[3];           // reference velocity of the stored deviations
+  float W[3][3];           // reference triplets Psi_c(uref, T + uref^2, lambda), c = -1, 0, 1
+  float WW[3][3];          // W[0][c0] * W[1][c1] (rounded from FP64)
+  float g[3];              // body-force acceleration
+  float T;
+  float omega;
+  float coef;              // (2 - omega)/(2 omega); 0 for the uncorrected control
+  float inv_scale;         // stored value * inv_scale = deviation
+  float scale;
+  float pad1;
+};
+
+struct TableHeader {
+  int32_t count;
+  int32_t pad;
+  int64_t total_tiles;
+};
+
+// FP64 constants of a lattice used by the (non-hot) conversion, init and
+// diagnostic kernels.
+struct LatticeConst64 {
+  int32_t D, Q;
+  int32_t n[3];            // physical extents (x, y, z), z = 1 for D2Q9
+  int32_t wall[3];         // physical axes
+  int64_t stride;
+  int64_t N;
+  double lam[3];           // physical axes
+  double T;
+  double uref[3];
+  double g[3];
+  double W[3][3];          // physical axes, reference triplets
+  double scale, inv_scale;
+  double mode_k[3];
+  double mode_dir[3];
+  int32_t storage;
+  int32_t has_mode;
+};
+
+// ---- launchers (defined in the .hip translation units) ----
+hipError_t launch_step(int D, int storage, bool wall, bool force, const TableHeader* hdr,
+                       const LatticeDesc* table, int64_t substep, int grid, hipStream_t st);
+int step_block_threads(int D);
+
+hipError_t launch_init(const LatticeConst64& c, const double* stage, int64_t cell0, int64_t count,
+                       void* dst, hipStream_t st);
+hipError_t launch_pop_out(const LatticeConst64& c, const void* src, int i, double* out, hipStream_t st);
+hipError_t launch_pop_in(const LatticeConst64& c, const double* in, int i, void* dst, hipStream_t st);
+hipError_t launch_field(const LatticeConst64& c, const void* src, int comp, double* out, hipStream_t st);
+// Diagnostics of the state in `src`: the record goes to `last`, and is also
+// appended to the ring `history` (capacity records, count in *hist_count)
+// when capacity > 0. `ustage` holds 3 N floats of scratch.
+hipError_t launch_diag(const LatticeConst64& c, const void* src, float* ustage, double* partials,
+                       double* history, int64_t* hist_count, int32_t capacity, double* last,
+                       int64_t step, hipStream_t st);
+
+}  // namespace elbm

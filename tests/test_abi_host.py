@@ -1,0 +1,88 @@
+"""C-ABI host checks that need no GPU: the library loads, exports every symbol
+include/elbm.h declares, validates parameters and computes the footprint."""
+import math
+
+import pytest
+
+from paper_2101_04550_amd import elbm as E
+
+
+def test_every_declared_symbol_is_exported():
+    declared = E.header_functions()
+    assert len(declared) >= 20
+    missing = [n for n in declared if not hasattr(E._lib, n)]
+    assert missing == []
+
+
+def test_abi_version_and_status_strings():
+    assert E._lib.elbm_abi_version() == E.ABI_VERSION
+    names = [E._lib.elbm_status_string(s).decode() for s in range(6)]
+    assert names == ["ELBM_OK", "ELBM_EINVAL", "ELBM_EUNSUPPORTED", "ELBM_ENOMEM", "ELBM_EDEVICE", "ELBM_EUNSTABLE"]
+    assert E._lib.elbm_status_string(99).decode() == "ELBM_UNKNOWN"
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(omega=2.0), "omega"),
+    (dict(omega=0.0), "omega"),
+    (dict(T=0.0), "T must"),
+    (dict(T=0.5, lam=(0.5, 1.0)), "rest weight"),   # Psi_0 = 1 - T/lam^2 < 0
+    (dict(n=(2, 64)), "periodic axis"),
+    (dict(n=(64, 1), walls=(False, True)), "bounce-back axis"),
+    (dict(lam=(0.0, 1.0)), "lambda"),
+    (dict(storage=7), "storage"),
+    (dict(diag_every=5, diag_capacity=0), "diag_capacity"),
+])
+def test_validation_rejects(kw, msg):
+    args = dict(n=(64, 64), T=1 / 3, omega=1.5)
+    args.update(kw)
+    p = E.make_params(**args)
+    assert E.validate(p) == E.EINVAL
+    assert msg in E._lib.elbm_last_error().decode()
+    with pytest.raises(E.ElbmError):
+        E.query_bytes(p)
+
+
+def test_validation_rejects_bad_lattice_shapes():
+    p = E.make_params((8, 8, 8), T=0.5, omega=1.0)
+    p.lattice = 15
+    assert E.validate(p) == E.EINVAL
+    p = E.make_params((8, 8), T=0.5, omega=1.0)
+    p.n[2] = 4
+    assert E.validate(p) == E.EINVAL
+    p = E.make_params((8, 8), T=0.5, omega=1.0)
+    p.abi_version = 99
+    assert E.validate(p) == E.EINVAL
+    p = E.make_params((2048, 2048, 1024), T=0.5, omega=1.0)
+    assert E.validate(p) == E.EINVAL  # more than 2^31 - 1 nodes
+
+
+@pytest.mark.parametrize("n,storage,es", [((64, 64), "f32", 4), ((256, 256, 256), "f32", 4),
+                                          ((384, 192, 192), "f16", 2), ((100, 77), "bf16", 2)])
+def test_footprint_covers_two_population_buffers(n, storage, es):
+    p = E.make_params(n, T=1 / 3, omega=1.5, storage=storage)
+    b = E.query_bytes(p)
+    Q = 9 if len(n) == 2 else 27
+    N = math.prod(n)
+    pops = 2 * Q * N * es
+    assert b >= pops
+    # fixed scratch (descriptor, partial sums, one record) stays small
+    assert b - pops < 2 * Q * 256 * es + 2 * 4096 + 256 * 1024
+    # history adds capacity * 16 doubles
+    p2 = E.make_params(n, T=1 / 3, omega=1.5, storage=storage, diag_every=10, diag_capacity=1000)
+    assert E.query_bytes(p2) - b >= 1000 * 16 * 8
+
+
+def test_last_error_is_thread_local():
+    import threading
+
+    E.validate(E.make_params((64, 64), T=1 / 3, omega=3.0))
+    seen = {}
+
+    def other():
+        seen["msg"] = E._lib.elbm_last_error().decode()
+
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert seen["msg"] == ""
+    assert "omega" in E._lib.elbm_last_error().decode()

@@ -1,0 +1,303 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs, element by element.
+
+Tolerances (FP32 arithmetic on deviations, FP64 oracle):
+* one step from an arbitrary state: max |f_gpu - f_oracle| <= 2e-7 and the
+  rel-L2 of the deviations f - w <= 2e-6;
+* ten steps: rel-L2 of the deviations <= 1e-5;
+* workload fields after 100 steps: rel-L2 of every non-uniform velocity
+  component <= 1e-5 with FP32 storage, <= 1e-3 with FP16 deviation storage;
+  BF16 storage (8 significand bits) is held to <= 1e-2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import inputs as I
+import oracle as O
+from gpu_helpers import dev_rel_l2, lattice_from_field, lib, oracle_init, params_for, random_state, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+ARBITRARY = {
+    "d2_periodic_ragged": dict(n=(300, 77), lam=(2.0, 1.0), T=0.45, omega=1.7),
+    "d2_walls_y_force": dict(n=(70, 33), T=1 / 3, omega=1.2, walls=(False, True), force=(1e-4, 0.0)),
+    "d2_walls_x_stretched": dict(n=(40, 50), lam=(1.4, 1.0), T=0.4, omega=1.5, walls=(True, False)),
+    "d2_control": dict(n=(64, 64), T=0.5, omega=1.8, extended=False),
+    "d3_periodic_ragged": dict(n=(70, 37, 21), lam=(1.4, 1.0, 2.0), T=0.4, omega=1.6),
+    "d3_channel": dict(n=(48, 24, 24), lam=(2.0, 1.0, 1.0), T=0.5, omega=1.9, walls=(False, True, False),
+                       force=(1e-5, 0.0, 0.0)),
+    "d3_walls_xz": dict(n=(20, 30, 18), T=1 / 3, omega=1.0, walls=(True, False, True)),
+    "d3_force_periodic": dict(n=(64, 16, 20), T=0.5, omega=1.3, force=(1e-4, -2e-4, 5e-5)),
+    "d3_min_periodic": dict(n=(3, 3, 3), T=0.3, omega=1.1),
+    "d3_min_walls": dict(n=(5, 2, 4), T=0.5, omega=1.4, walls=(False, True, False)),
+    "d3_control_stretched": dict(n=(32, 40, 24), lam=(2.0, 1.0, 1.0), T=1 / 3, omega=1.7, extended=False),
+}
+
+
+@pytest.mark.parametrize("case", sorted(ARBITRARY))
+def test_arbitrary_state_one_and_ten_steps(case):
+    E = lib()
+    p = O.Params(**ARBITRARY[case])
+    f0 = random_state(p, seed=hash(case) % 1000)
+    lat = E.Lattice(params_for(p))
+    lat.set_populations(f0)
+    g0 = lat.populations()  # the GPU's (FP32-rounded) initial state
+    assert np.abs(g0 - f0).max() < 1e-8
+    lat.step(1)
+    g1 = lat.populations()
+    o1 = O.step(g0, p)
+    assert np.abs(g1 - o1).max() <= 2e-7, case
+    assert dev_rel_l2(g1, o1, p) <= 2e-6, case
+    lat.step(9)
+    g10 = lat.populations()
+    o10 = O.run(o1, p, 9)
+    assert dev_rel_l2(g10, o10, p) <= 1e-5, case
+    # macroscopic fields agree with the oracle's moments of the same state
+    rho, u = lat.fields()
+    ro, uo = O.velocity(o10, p)
+    assert np.abs(rho - ro).max() < 1e-6
+    assert np.abs(u - uo).max() < 1e-6
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_init_matches_equilibrium(storage):
+    """f'(0) = f^eq(rho, u + u_adv) (Sec. 2.3, eq. 27eq), rounded once to the storage format."""
+    p = O.Params(n=(40, 24, 10), lam=(2.0, 1.0, 1.0), T=0.5, omega=1.5)
+    g = I.rng(77)
+    fld = I.Field(1.0 + 0.01 * g.standard_normal((10, 24, 40)), 0.05 * g.standard_normal((3, 10, 24, 40)),
+                  p.n, p.lam)
+    uadv = (0.03, -0.01, 0.02)
+    lat = lattice_from_field(p, fld, storage, u_adv=uadv)
+    fo = oracle_init(p, fld, u_adv=uadv)
+    w = O.reference_weights(p, uadv).reshape((-1, 1, 1, 1))
+    h = fo - w
+    tol = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}[storage]
+    err = np.abs(lat.populations() - fo)
+    assert (err <= tol * np.abs(h) + 1e-12).all()
+
+
+def _cfg1(T, storage, via_uadv):
+    fld = I.shear_wave_axis((64, 64), U0=0.0 if via_uadv else 0.1, A=0.01)
+    uadv = (0.1, 0.0) if via_uadv else None
+    p = O.Params(n=(64, 64), T=T, omega=1.8)
+    lat = lattice_from_field(p, fld, storage, u_adv=uadv)
+    fo = oracle_init(p, fld, u_adv=uadv)
+    lat.step(100)
+    fo = O.run(fo, p, 100)
+    rho, u = lat.fields()
+    _, uo = O.velocity(fo, p)
+    return rel_l2(u[1], uo[1]), np.abs(u[0] - 0.1).max()
+
+
+@pytest.mark.parametrize("T", [1 / 3, 0.5])
+@pytest.mark.parametrize("via_uadv", [True, False])
+def test_cfg1_shear_wave_fp32(T, via_uadv):
+    """D2Q9 64x64, U0 = 0.1, A = 0.01, omega = 1.8, 100 steps: rel-L2(u_y) <= 1e-5."""
+    e, ux = _cfg1(T, "f32", via_uadv)
+    assert e <= 1e-5
+    assert ux <= 1e-6
+
+
+@pytest.mark.parametrize("T", [1 / 3, 0.5])
+def test_cfg1_shear_wave_fp16(T):
+    e, ux = _cfg1(T, "f16", True)
+    assert e <= 1e-3
+    assert ux <= 1e-4
+
+
+def test_cfg1_shear_wave_bf16():
+    e, _ = _cfg1(1 / 3, "bf16", True)
+    assert e <= 1e-2
+
+
+_hit_cache = {}
+
+
+def _hit_oracle():
+    if "fo" not in _hit_cache:
+        fld = I.hit_field(64, k0=4.0, urms=0.05)
+        p = O.Params(n=(64, 64, 64), T=0.5, omega=1.892885)
+        fo = O.run(oracle_init(p, fld), p, 100)
+        _hit_cache.update(fld=fld, p=p, fo=fo)
+    return _hit_cache["fld"], _hit_cache["p"], _hit_cache["fo"]
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 1e-3), ("bf16", 1e-2)])
+def test_hit_64_cube(storage, tol):
+    """D3Q27 decaying turbulence, 64^3, T = 0.5, u_rms = 0.05, 100 steps."""
+    fld, p, fo = _hit_oracle()
+    lat = lattice_from_field(p, fld, storage)
+    lat.step(100)
+    _, u = lat.fields()
+    _, uo = O.velocity(fo, p)
+    for a in range(3):
+        assert rel_l2(u[a], uo[a]) <= tol, (storage, a)
+
+
+_chan_cache = {}
+
+
+def _channel():
+    if "fo" not in _chan_cache:
+        n, lam = (96, 48, 48), (2.0, 1.0, 1.0)
+        H = 0.5 * n[1] * lam[1]
+        omega = 1.976785
+        nu = (1 / omega - 0.5) * 0.5
+        g = 180.0 ** 2 * nu ** 2 / H ** 3
+        fld = I.channel_field(n, lam)
+        p = O.Params(n=n, lam=lam, T=0.5, omega=omega, walls=(False, True, False), force=(g, 0.0, 0.0))
+        fo = O.run(oracle_init(p, fld), p, 100)
+        _chan_cache.update(fld=fld, p=p, fo=fo)
+    return _chan_cache["fld"], _chan_cache["p"], _chan_cache["fo"]
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 1e-3)])
+def test_channel_stretched_walls_force(storage, tol):
+    """D3Q27 lam = (2,1,1), bounce-back in y, body force, 96x48x48, 100 steps."""
+    fld, p, fo = _channel()
+    lat = lattice_from_field(p, fld, storage)
+    lat.step(100)
+    _, u = lat.fields()
+    _, uo = O.velocity(fo, p)
+    for a in range(3):
+        assert rel_l2(u[a], uo[a]) <= tol, (storage, a)
+
+
+def test_double_shear_layer_256():
+    """D2Q9 double shear layer (Re = 30000 scaled to L = 256 at constant nu), 100 steps."""
+    fld = I.double_shear_layer((256, 256))
+    p = O.Params(n=(256, 256), T=0.5, omega=1.973061)
+    lat = lattice_from_field(p, fld)
+    lat.step(100)
+    fo = O.run(oracle_init(p, fld), p, 100)
+    _, u = lat.fields()
+    _, uo = O.velocity(fo, p)
+    assert rel_l2(u[0], uo[0]) <= 1e-5
+    assert rel_l2(u[1], uo[1]) <= 1e-5
+
+
+def test_diagnostics_match_oracle():
+    """FP64 reductions on the GPU against the oracle's, same state."""
+    fld = I.shear_wave_rotated((32, 64), (2.0, 1.0), U0=0.05, a0=1e-3)
+    p = O.Params(n=(32, 64), lam=(2.0, 1.0), T=1 / 3, omega=1.8)
+    lat = lattice_from_field(p, fld)
+    lat.step(37)
+    d = lat.diag()
+    f = lat.populations()
+    do = O.diagnostics(f, p, fld.mode_k, fld.mode_dir)
+    assert d["step"] == 37
+    assert abs(d["mass"] - do.mass) <= 1e-12 * do.mass
+    for a in range(2):
+        assert abs(d["mom"][a] - do.mom[a]) <= 1e-10
+    assert abs(d["ke"] / do.ke - 1) <= 1e-6
+    assert abs(d["enstrophy"] / do.enstrophy - 1) <= 1e-5
+    assert abs(d["mode"] - do.mode) <= 1e-6 * abs(do.mode)
+    assert abs(d["max_uperp"] / do.max_uperp - 1) <= 1e-6
+    assert abs(d["min_rho"] - do.min_rho) <= 1e-7
+    assert d["nan_count"] == 0
+
+
+def test_diagnostics_3d_walls_force():
+    fld = I.channel_field((48, 24, 24), (2.0, 1.0, 1.0))
+    p = O.Params(n=(48, 24, 24), lam=(2.0, 1.0, 1.0), T=0.5, omega=1.9, walls=(False, True, False),
+                 force=(1e-5, 0.0, 0.0))
+    lat = lattice_from_field(p, fld)
+    lat.step(5)
+    d = lat.diag()
+    do = O.diagnostics(lat.populations(), p)
+    assert abs(d["mass"] / do.mass - 1) <= 1e-12
+    for a in range(3):
+        assert abs(d["mom"][a] - do.mom[a]) <= 1e-9
+    assert abs(d["ke"] / do.ke - 1) <= 1e-6
+    assert abs(d["enstrophy"] / do.enstrophy - 1) <= 1e-5
+
+
+def _gpu_viscosity(n, lam, T, U0, storage, extended=True, steps=500, every=5, a0=1e-3, rotated=True):
+    if rotated:
+        fld = I.shear_wave_rotated(n, lam, U0=0.0, a0=a0)
+        s2 = math.sqrt(0.5)
+        uadv = (U0 * s2, U0 * s2)
+    else:
+        fld = I.shear_wave_axis(n, U0=0.0, A=a0)
+        uadv = (U0, 0.0)
+    p = O.Params(n=n, lam=lam, T=T, omega=1.8, extended=extended)
+    lat = lattice_from_field(p, fld, storage, u_adv=uadv, diag_every=every, diag_capacity=steps // every)
+    lat.step(steps)
+    hist = lat.diag_history()
+    t = [h["step"] for h in hist]
+    amp = [abs(h["mode"]) for h in hist]
+    k2 = sum(k * k for k in fld.mode_k)
+    return O.fit_decay_rate(t, amp, 50) / k2 / p.nu
+
+
+@pytest.mark.parametrize("T", [1 / 3, 0.5])
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_viscosity_cfg1_on_gpu(T, storage):
+    """Sec. 3.1: fitted decay of the axis-aligned wave gives nu = (1/omega - 1/2) T within 1%."""
+    r = _gpu_viscosity((64, 64), (1.0, 1.0), T, 0.1, storage, rotated=False, a0=0.01)
+    assert abs(r - 1) < 1e-2
+
+
+@pytest.mark.parametrize("U0", [0.0, 0.173])
+def test_galilean_invariance_on_gpu(U0):
+    r = _gpu_viscosity((64, 64), (1.0, 1.0), 1 / 3, U0, "f32")
+    assert abs(r - 1) < 1e-2
+
+
+def test_isotropy_stretched_on_gpu_and_control():
+    """Extended model recovers nu on lam = (2,1); the uncorrected control shows the
+    predicted hyper-viscosity 1 + (lam_x^2 - 3T)/(4T) = 3.25."""
+    r = _gpu_viscosity((64, 128), (2.0, 1.0), 1 / 3, 0.1, "f32", steps=600)
+    assert abs(r - 1) < 1e-2
+    rc = _gpu_viscosity((32, 64), (2.0, 1.0), 1 / 3, 0.0, "f32", extended=False)
+    assert abs(rc / 3.25 - 1) < 0.1
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_runs_are_deterministic_and_checkpoint_resumes_bitwise(storage):
+    E = lib()
+    fld = I.hit_field(32, k0=4.0, urms=0.05, seed_offset=9)
+    p = O.Params(n=(32, 32, 32), T=0.5, omega=1.7)
+    a = lattice_from_field(p, fld, storage)
+    b = lattice_from_field(p, fld, storage)
+    a.step(40)
+    b.step(20)
+    ck = b.save()
+    c = E.Lattice(params_for(p, storage))
+    c.load(ck)
+    assert c.step_count == 20
+    c.step(20)
+    b.step(20)
+    fa, fb, fc = a.populations(), b.populations(), c.populations()
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(fa, fc)
+
+
+def test_error_paths():
+    E = lib()
+    import torch
+
+    p = O.Params(n=(64, 64), T=1 / 3, omega=1.5)
+    ep = params_for(p)
+    small = torch.empty(E.query_bytes(ep) - 4096, dtype=torch.uint8, device="cuda")
+    with pytest.raises(E.ElbmError) as ei:
+        E.Lattice(ep, buffer=small)
+    assert ei.value.status == E.ENOMEM
+    big = torch.empty(E.query_bytes(ep) + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(E.ElbmError) as ei:
+        E.Lattice(ep, buffer=big[4:])
+    assert ei.value.status == E.EINVAL
+    lat = E.Lattice(ep)
+    f = O.init_state(np.ones((64, 64)), np.zeros((2, 64, 64)), p)
+    f[3, 10, 10] = np.nan
+    lat.set_populations(f)
+    with pytest.raises(E.ElbmError) as ei:
+        lat.diag()
+    assert ei.value.status == E.EUNSTABLE
+    d = lat.diag(check=False)
+    assert d["nan_count"] == 1
+    other = E.Lattice(params_for(O.Params(n=(64, 32), T=1 / 3, omega=1.5)))
+    with pytest.raises(E.ElbmError):
+        other.load(lat.save())
