@@ -1,0 +1,264 @@
+"""Benchmark of the extended-LBGK hot path on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): D3Q27 decaying
+homogeneous isotropic turbulence, 256^3 periodic, cubic lattice, T = 0.5,
+omega = 1.892885 (Re_lambda = 72 for the k0 = 4 spectrum), u_rms = 0.05,
+rho = 1, seeded solenoidal field with E(k) ~ k^4 exp(-2 (k/k0)^2). One step is
+one fused stream-and-collide launch over the whole lattice; FP64 kinetic
+energy / enstrophy reductions run every 50 steps inside the timed region,
+as in the workload. Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: MLUPS (FP32 deviation storage) as `value`, the FP16 and
+BF16 deviation-storage runs of the same workload beside it, the roofline of
+the step kernel (algorithmic bytes 2 Q s per node, measured with HIP events on
+the launch stream), and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "D3Q27 MLUPS & % HBM roofline, FP32 vs FP16-store; served solves/s + p99"
+N_HIT = 256
+OMEGA_HIT = 1.892885
+T_HIT = 0.5
+DIAG_EVERY = 50
+PMC_FILE = os.path.join(ROOT, "profiles", "step_d3q27_f32_hit256_pmc.txt")
+STEP_SOURCE = os.path.join(ROOT, "paper_2101_04550_amd", "csrc", "elbm_step.hip")
+
+
+def parse_args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storages", default="f32,f16,bf16")
+    ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
+    ap.add_argument("--n", type=int, default=N_HIT, help="cube edge (default 256)")
+    ap.add_argument("--kernel-reps", type=int, default=200, help="step launches timed for the roofline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def step_source_hash():
+    with open(STEP_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def read_pmc_traffic():
+    """HBM bytes per step launch from the committed rocprofv3 counter summary,
+    scaled by the copy-kernel calibration; None if absent or stale."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    kv = {}
+    for line in open(PMC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv.get("step_source_sha256") != step_source_hash():
+            return None
+        fetch = float(kv["step_fetch_kib_per_dispatch"]) * 1024 / float(kv["copy_fetch_factor"])
+        write = float(kv["step_write_kib_per_dispatch"]) * 1024 / float(kv["copy_write_factor"])
+        return fetch + write
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+
+
+def calibrate_copy():
+    import torch
+
+    n = 1 << 29  # 2 GiB of fp32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": n * 4, "bytes_written": n * 4, "launches": 5}))
+
+
+def run_gpu(storage, fld, steps, warmup, kernel_reps):
+    import torch
+
+    from paper_2101_04550_amd import elbm as E
+
+    n = fld.n
+    N = math.prod(n)
+    params = E.make_params(n, T=T_HIT, omega=OMEGA_HIT, storage=storage, diag_every=DIAG_EVERY,
+                           diag_capacity=max(1, (steps + warmup) // DIAG_EVERY + 1))
+    lat = E.Lattice(params)
+    lat.init(fld.rho, fld.u)
+    stream = lat.stream
+    lat.step(warmup)
+    lat.sync()
+    # whole-job timed region: K steps incl. the FP64 diagnostics every 50 steps
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    lat.step(steps)
+    t1.record(stream)
+    t1.synchronize()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    hist = lat.diag_history()
+    lat.close()
+    del lat
+    # step-kernel duration: same lattice shape, diagnostics off, events on the
+    # launch stream around kernel_reps back-to-back step launches
+    p2 = E.make_params(n, T=T_HIT, omega=OMEGA_HIT, storage=storage)
+    lat = E.Lattice(p2)
+    lat.init(fld.rho, fld.u)
+    lat.step(5)
+    lat.sync()
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    k0.record(lat.stream)
+    lat.step(kernel_reps)
+    k1.record(lat.stream)
+    k1.synchronize()
+    kms = k0.elapsed_time(k1) / kernel_reps
+    d = lat.diag()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    es = 4 if storage == "f32" else 2
+    alg_bytes = 2 * 27 * es * N
+    return {
+        "storage": storage,
+        "mlups": N * steps / (ms * 1e-3) / 1e6,
+        "ms_per_step": ms / steps,
+        "kernel_ms": kms,
+        "kernel_gbs": alg_bytes / (kms * 1e-3) / 1e9,
+        "alg_bytes_per_launch": alg_bytes,
+        "ke_first": hist[0]["ke"] if hist else None,
+        "ke_last": hist[-1]["ke"] if hist else None,
+        "enstrophy_last": hist[-1]["enstrophy"] if hist else None,
+        "final_min_rho": d["min_rho"],
+    }
+
+
+def cpu_baseline(seconds_budget=20.0):
+    """The FP64 NumPy oracle (untuned) on a bounded sample of the same workload:
+    a 96^3 box of the same spectrum (k0 = 4), timed over whole steps."""
+    import numpy as np
+
+    import inputs as I
+    import oracle as O
+
+    n = 96
+    fld = I.hit_field(n, k0=4.0, urms=0.05)
+    p = O.Params(n=(n, n, n), T=T_HIT, omega=OMEGA_HIT)
+    f = O.init_state(fld.rho, fld.u, p)
+    f = O.step(f, p)  # warm caches / allocator
+    steps = 0
+    t = time.perf_counter()
+    while True:
+        f = O.step(f, p)
+        steps += 1
+        if time.perf_counter() - t > seconds_budget or steps >= 200:
+            break
+    dt = time.perf_counter() - t
+    assert np.isfinite(f).all()
+    cpu = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {
+        "value": n ** 3 * steps / dt / 1e6,
+        "unit": "MLUPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"D3Q27 HIT {n}^3 (k0=4, T=0.5, omega={OMEGA_HIT}), {steps} FP64 NumPy steps in "
+                  f"{dt:.1f} s on one core of {cpu} ({os.cpu_count()} logical CPUs visible)",
+    }
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the lattice is not sharded across GPUs in this build)", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    import torch
+
+    import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    fld = I.hit_field(args.n, k0=4.0, urms=0.05)
+    runs = {}
+    for s in [x for x in args.storages.split(",") if x]:
+        runs[s] = run_gpu(s, fld, args.steps, args.warmup, args.kernel_reps)
+        print(f"# {s}: {runs[s]['mlups']:.1f} MLUPS, step kernel {runs[s]['kernel_ms']:.4f} ms "
+              f"= {runs[s]['kernel_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    main_run = runs.get("f32") or next(iter(runs.values()))
+    N = args.n ** 3
+    traffic = read_pmc_traffic() if (args.n == N_HIT and main_run["storage"] == "f32") else None
+    out = {
+        "metric": METRIC,
+        "value": round(main_run["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_run["storage"],
+        "data": "synthetic",
+        "config": {
+            "workload": f"D3Q27 decaying HIT {args.n}^3 periodic, cubic lattice, T=0.5, omega={OMEGA_HIT}, "
+                        f"u_rms=0.05, k0=4; {main_run['storage'].upper()} deviation storage; FP64 KE/enstrophy "
+                        f"every {DIAG_EVERY} steps",
+            "lattice": "D3Q27",
+            "cells": N,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(main_run["kernel_gbs"], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(main_run["kernel_gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic / (main_run["kernel_ms"] * 1e-3) / 1e9, 1),
+            "kernel": "step_kernel<D3Q27, f32, periodic, no force>",
+            "kernel_ms": round(main_run["kernel_ms"], 5),
+            "alg_bytes_per_launch": main_run["alg_bytes_per_launch"],
+        },
+        "storage_variants": {
+            s: {"mlups": round(r["mlups"], 1), "kernel_ms": round(r["kernel_ms"], 5),
+                "kernel_gbs": round(r["kernel_gbs"], 1),
+                "vs_f32": round(r["mlups"] / main_run["mlups"], 3)}
+            for s, r in runs.items()
+        },
+        "diagnostics": {s: {"ke_first": r["ke_first"], "ke_last": r["ke_last"],
+                            "enstrophy_last": r["enstrophy_last"], "min_rho": r["final_min_rho"]}
+                        for s, r in runs.items()},
+    }
+    if not args.skip_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

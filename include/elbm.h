@@ -231,7 +231,10 @@ int32_t elbm_destroy(elbm_handle h);
  * once into a HIP graph (cached by that length) and replayed; the table is
  * uploaded before each replay. Automatic diagnostics are not recorded in a
  * batch run. All lattices must live on the batch's device; none may appear
- * twice. The batch allocates its own device memory (library-owned). */
+ * twice. The batch allocates its own device memory, pinned host staging and
+ * a non-blocking stream (library-owned); `hip_stream` (may be NULL) is only
+ * used for ordering: a run starts after the work queued on it and on the
+ * lattices' streams, and they wait for the run's end. */
 int32_t elbm_batch_create(int32_t capacity, void* hip_stream, elbm_batch* out);
 int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps,
                        int32_t count, int32_t use_graph);

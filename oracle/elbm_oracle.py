@@ -41,6 +41,7 @@ their docstring ("parity unpinned").
 
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass, field
 
@@ -307,11 +308,16 @@ def reference_weights(p: Params, u_ref=None):
 # Single-node update (used to check full-size runs at sampled nodes)
 # ----------------------------------------------------------------------------
 
+@functools.lru_cache(maxsize=None)
+def _opposite_of_set(D):
+    return opposite(velocity_set(D))
+
+
 def _pull_node(fpost, c, walls, idx):
     """Post-streaming populations at one node (array index tuple)."""
     Q, D = c.shape
     grid = fpost.shape[1:]
-    opp = opposite(c)
+    opp = _opposite_of_set(D)
     out = np.empty(Q)
     for i in range(Q):
         src = list(idx)

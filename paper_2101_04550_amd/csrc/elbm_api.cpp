@@ -44,7 +44,9 @@ struct elbm_lattice {
 
 struct elbm_batch_s {
   int capacity = 0, device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t caller = nullptr;  // ordering only: the batch waits for it and it waits for the batch
+  hipStream_t stream = nullptr;  // the batch's own non-blocking stream (capturable)
+  hipEvent_t entry = nullptr;
   hipEvent_t copied = nullptr;
   hipEvent_t done = nullptr;
   bool copy_pending = false;
@@ -131,6 +133,7 @@ int32_t check(const elbm_params* p) {
     if (N > std::numeric_limits<int32_t>::max())
       return fail(ELBM_EINVAL, "too many nodes: at most 2^31 - 1 per lattice");
   }
+  if (p->n[0] * p->n[1] >= (int64_t(1) << 30)) return fail(ELBM_EINVAL, "n_x * n_y must stay below 2^30");
   if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(ELBM_EINVAL, "T must be positive and finite");
   if (!(p->omega > 0.0 && p->omega < 2.0)) return fail(ELBM_EINVAL, "omega must lie in (0, 2)");
   for (int a = 0; a < D; ++a) {
@@ -607,14 +610,18 @@ int32_t elbm_batch_create(int32_t capacity, void* hip_stream, elbm_batch* out) {
   auto* b = new (std::nothrow) elbm_batch_s();
   if (!b) return fail(ELBM_EINVAL, "out of host memory");
   b->capacity = capacity;
-  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->caller = static_cast<hipStream_t>(hip_stream);
   const size_t tbytes = align_up(sizeof(TableHeader), 64) + size_t(capacity) * sizeof(LatticeDesc);
   hipError_t e = hipGetDevice(&b->device);
+  // a stream of its own: the legacy default stream cannot be captured into a graph
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->host_stage), tbytes * kClasses);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->entry, hipEventDisableTiming);
   if (e != hipSuccess) {
     if (b->host_stage) (void)hipHostFree(b->host_stage);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return hip_fail(e, "elbm_batch_create");
   }
@@ -683,7 +690,9 @@ int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps
     while (g < base && g < 4096) g *= 2;
     grids.push_back(int(g));
   }
-  // order the device work after what is pending on the lattices' streams
+  // order the device work after what is pending on the caller's and the lattices' streams
+  HIPCHK(hipEventRecord(b->entry, b->caller));
+  HIPCHK(hipStreamWaitEvent(b->stream, b->entry, 0));
   for (int32_t k = 0; k < count; ++k) {
     HIPCHK(hipEventRecord(hs[k]->event, hs[k]->stream));
     HIPCHK(hipStreamWaitEvent(b->stream, hs[k]->event, 0));
@@ -742,6 +751,7 @@ int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps
     if (s) return s;
   }
   HIPCHK(hipEventRecord(b->done, b->stream));
+  HIPCHK(hipStreamWaitEvent(b->caller, b->done, 0));
   for (int32_t k = 0; k < count; ++k) {
     hs[k]->step += steps[k];
     HIPCHK(hipStreamWaitEvent(hs[k]->stream, b->done, 0));
@@ -758,6 +768,8 @@ int32_t elbm_batch_destroy(elbm_batch b) {
   if (b->host_stage) (void)hipHostFree(b->host_stage);
   (void)hipEventDestroy(b->copied);
   (void)hipEventDestroy(b->done);
+  (void)hipEventDestroy(b->entry);
+  (void)hipStreamDestroy(b->stream);
   delete b;
   return ELBM_OK;
 }

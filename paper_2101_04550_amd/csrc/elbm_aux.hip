@@ -113,29 +113,40 @@ __global__ void pop_in_kernel(LatticeConst64 c, const double* __restrict__ in, i
 
 // FP64 moments of one node of the stored state: rho and the reported
 // velocity u = j/rho - g/2 (j the stored, post-force momentum).
-template <int S>
+template <int S, int D>
 __device__ __forceinline__ void node_moments(const LatticeConst64& c, const typename Raw<S>::T* src, int64_t cell,
                                              double& rho, double (&u)[3]) {
+  constexpr int Q = D == 3 ? 27 : 9;
+  double h[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) h[i] = Raw<S>::get(src + i * c.stride + cell);
   double dr = 0.0, dj[3] = {0.0, 0.0, 0.0};
-  for (int i = 0; i < c.Q; ++i) {
-    const double h = Raw<S>::get(src + i * c.stride + cell) * c.inv_scale;
-    dr += h;
-    for (int a = 0; a < c.D; ++a) dj[a] += cdir(i, a) * h;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    dr += h[i];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int ci = (i / (a == 0 ? 1 : (a == 1 ? 3 : 9))) % 3 - 1;
+      if (ci > 0) dj[a] += h[i];
+      if (ci < 0) dj[a] -= h[i];
+    }
   }
+  dr *= c.inv_scale;
   rho = 1.0 + dr;
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     u[a] = 0.0;
-    if (a < c.D) u[a] = (c.uref[a] + c.lam[a] * dj[a]) / rho - 0.5 * c.g[a];
+    if (a < D) u[a] = (c.uref[a] + c.lam[a] * dj[a] * c.inv_scale) / rho - 0.5 * c.g[a];
   }
 }
 
-template <int S>
+template <int S, int D>
 __global__ void field_kernel(LatticeConst64 c, const void* __restrict__ srcv, int comp, double* __restrict__ out) {
   using T = typename Raw<S>::T;
   const T* src = static_cast<const T*>(srcv);
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < c.N; k += int64_t(gridDim.x) * blockDim.x) {
     double rho, u[3];
-    node_moments<S>(c, src, k, rho, u);
+    node_moments<S, D>(c, src, k, rho, u);
     out[k] = comp == 0 ? rho : u[comp - 1];
   }
 }
@@ -179,7 +190,7 @@ __device__ double block_reduce(double x, int kind, double* sh) {
 
 __device__ __forceinline__ int field_kind(int f) { return f == R_MAXU ? 1 : (f == R_MINRHO ? 2 : 0); }
 
-template <int S>
+template <int S, int D>
 __global__ void __launch_bounds__(kDiagThreads)
     diag_moments_kernel(LatticeConst64 c, const void* __restrict__ srcv, float* __restrict__ ustage,
                         double* __restrict__ partials) {
@@ -193,7 +204,7 @@ __global__ void __launch_bounds__(kDiagThreads)
   const int nx = c.n[0], ny = c.n[1];
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < c.N; k += int64_t(gridDim.x) * blockDim.x) {
     double rho, u[3];
-    node_moments<S>(c, src, k, rho, u);
+    node_moments<S, D>(c, src, k, rho, u);
     const bool finite = isfinite(rho) && isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]);
     acc[R_NAN] += finite ? 0.0 : 1.0;
     acc[R_MASS] += rho;
@@ -335,24 +346,42 @@ hipError_t launch_pop_in(const LatticeConst64& c, const double* in, int i, void*
   return hipGetLastError();
 }
 
-hipError_t launch_field(const LatticeConst64& c, const void* src, int comp, double* out, hipStream_t st) {
+template <int S>
+void field_s(const LatticeConst64& c, const void* src, int comp, double* out, hipStream_t st) {
   const int g = grid_for(c.N, 256);
+  if (c.D == 3)
+    hipLaunchKernelGGL((field_kernel<S, 3>), dim3(g), dim3(256), 0, st, c, src, comp, out);
+  else
+    hipLaunchKernelGGL((field_kernel<S, 2>), dim3(g), dim3(256), 0, st, c, src, comp, out);
+}
+
+hipError_t launch_field(const LatticeConst64& c, const void* src, int comp, double* out, hipStream_t st) {
   switch (c.storage) {
-    case 0: hipLaunchKernelGGL(field_kernel<0>, dim3(g), dim3(256), 0, st, c, src, comp, out); break;
-    case 1: hipLaunchKernelGGL(field_kernel<1>, dim3(g), dim3(256), 0, st, c, src, comp, out); break;
-    case 2: hipLaunchKernelGGL(field_kernel<2>, dim3(g), dim3(256), 0, st, c, src, comp, out); break;
+    case 0: field_s<0>(c, src, comp, out, st); break;
+    case 1: field_s<1>(c, src, comp, out, st); break;
+    case 2: field_s<2>(c, src, comp, out, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int S>
+void diag_s(const LatticeConst64& c, const void* src, float* ustage, double* partials, hipStream_t st) {
+  if (c.D == 3)
+    hipLaunchKernelGGL((diag_moments_kernel<S, 3>), dim3(kDiagBlocks), dim3(kDiagThreads), 0, st, c, src, ustage,
+                       partials);
+  else
+    hipLaunchKernelGGL((diag_moments_kernel<S, 2>), dim3(kDiagBlocks), dim3(kDiagThreads), 0, st, c, src, ustage,
+                       partials);
 }
 
 hipError_t launch_diag(const LatticeConst64& c, const void* src, float* ustage, double* partials, double* history,
                        int64_t* hist_count, int32_t capacity, double* last, int64_t step, hipStream_t st) {
   const int nb = kDiagBlocks;
   switch (c.storage) {
-    case 0: hipLaunchKernelGGL(diag_moments_kernel<0>, dim3(nb), dim3(kDiagThreads), 0, st, c, src, ustage, partials); break;
-    case 1: hipLaunchKernelGGL(diag_moments_kernel<1>, dim3(nb), dim3(kDiagThreads), 0, st, c, src, ustage, partials); break;
-    case 2: hipLaunchKernelGGL(diag_moments_kernel<2>, dim3(nb), dim3(kDiagThreads), 0, st, c, src, ustage, partials); break;
+    case 0: diag_s<0>(c, src, ustage, partials, st); break;
+    case 1: diag_s<1>(c, src, ustage, partials, st); break;
+    case 2: diag_s<2>(c, src, ustage, partials, st); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();

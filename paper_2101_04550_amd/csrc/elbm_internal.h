@@ -16,10 +16,16 @@
 
 namespace elbm {
 
-constexpr int kTileX3 = 64;        // x width of a D3Q27 tile: one wavefront
-constexpr int kRows3 = 8;          // y rows of a D3Q27 tile -> 512 threads
+#ifndef ELBM_TX3
+#define ELBM_TX3 64
+#endif
+#ifndef ELBM_TY3
+#define ELBM_TY3 8
+#endif
+constexpr int kTileX3 = ELBM_TX3;  // x width of a D3Q27 tile
+constexpr int kRows3 = ELBM_TY3;   // y rows of a D3Q27 tile
 constexpr int kStrips2 = 4;        // 64-wide strips of a D2Q9 tile -> 256 threads
-constexpr int kDiagBlocks = 512;   // fixed grid of the diagnostic reductions
+constexpr int kDiagBlocks = 1024;  // fixed grid of the diagnostic reductions
 constexpr int kRec = 16;           // doubles per diagnostic record / partial
 constexpr float kF16Scale = 4096.0f;
 

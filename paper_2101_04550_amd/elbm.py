@@ -13,6 +13,11 @@ import re
 
 import numpy as np
 
+# torch must be loaded first: it brings the HIP runtime its tensors and streams
+# belong to, and libelbm must bind to that same runtime instance (a second
+# libamdhip64 in the process would not see the device).
+import torch  # noqa: F401
+
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_PKG)
 LIB_PATH = os.path.join(_PKG, "libelbm.so")

