@@ -181,18 +181,29 @@ Layout layout_of(const elbm_params* p) {
   return L;
 }
 
-// Marched-axis chunk: aim at about 1024 tiles (a few blocks per CU) without
-// making the ring-end overhead (2 extra planes per chunk) large.
-int choose_chunk(int D, int64_t t01, int n2) {
+// Marched-axis chunk. A tile of `chunk` planes costs about chunk + 2 plane
+// updates (the ring pulls one plane before and one after the chunk); tiles
+// run in rounds of `slots` resident blocks. Pick the number of chunks that
+// minimises rounds * (chunk + 2). ELBM_CHUNK overrides (for measurements).
+int choose_chunk(int D, int64_t t01, int n2, int64_t slots) {
   if (const char* s = std::getenv("ELBM_CHUNK")) {
     const int v = std::atoi(s);
     if (v > 0) return std::min(v, n2);
   }
-  const int minc = D == 3 ? 16 : 8;
-  const int64_t want_chunks = std::max<int64_t>(1, (1024 + t01 - 1) / t01);
-  int chunk = int((n2 + want_chunks - 1) / want_chunks);
-  chunk = std::max(chunk, minc);
-  return std::min(chunk, n2);
+  const int minc = std::min(n2, D == 3 ? 16 : 4);
+  int best = n2;
+  double best_cost = 1e300;
+  for (int chunk = n2; chunk >= minc; --chunk) {
+    const int64_t nc = (n2 + chunk - 1) / chunk;
+    if (chunk != (n2 + nc - 1) / nc) continue;  // only the smallest chunk for each chunk count
+    const int64_t rounds = (t01 * nc + slots - 1) / slots;
+    const double cost = double(rounds) * double(chunk + 2);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = chunk;
+    }
+  }
+  return best;
 }
 
 void fill_desc(elbm_lattice* h) {
@@ -207,16 +218,18 @@ void fill_desc(elbm_lattice* h) {
     const double ur = pa >= 0 ? p.u_adv[pa] : 0.0;
     d.n[a] = pa >= 0 ? int32_t(p.n[pa]) : 1;
     d.wall[a] = pa >= 0 ? (p.bc[pa] == ELBM_BC_BOUNCEBACK) : 0;
+    const double scale = p.storage == ELBM_STORE_F16 ? double(kF16Scale) : 1.0;
     d.lam[a] = float(lam);
     d.inv_lam[a] = float(1.0 / lam);
     d.inv_lam2[a] = float(1.0 / (lam * lam));
     d.half_inv_lam[a] = float(0.5 / lam);
+    d.mfac[a] = float(lam / scale);
     d.anom[a] = pa >= 0 ? float(lam * lam - 3.0 * p.T) : 0.f;
     d.uref[a] = float(ur);
     d.g[a] = pa >= 0 ? float(p.force[pa]) : 0.f;
-    for (int c = -1; c <= 1; ++c) {
+    // reference triplet (Sec. 2.2) at rho = 1, u = uref, P = T + uref^2
+    for (int c = -1; c <= 1; ++c)
       d.W[a][c + 1] = pa >= 0 ? float(psi(c, ur, p.T + ur * ur, lam)) : (c == 0 ? 1.f : 0.f);
-    }
   }
   for (int c0 = -1; c0 <= 1; ++c0)
     for (int c1 = -1; c1 <= 1; ++c1) {
@@ -228,6 +241,8 @@ void fill_desc(elbm_lattice* h) {
   d.omega = float(p.omega);
   d.coef = p.extended ? float((2.0 - p.omega) / (2.0 * p.omega)) : 0.f;
   const double scale = p.storage == ELBM_STORE_F16 ? double(kF16Scale) : 1.0;
+  d.om1 = float(1.0 - p.omega);
+  d.oms = float(p.omega * scale);
   d.scale = float(scale);
   d.inv_scale = float(1.0 / scale);
   d.buf[0] = h->buf[0];
@@ -237,7 +252,11 @@ void fill_desc(elbm_lattice* h) {
   const int tyr = D == 3 ? kRows3 : 1;
   d.tiles[0] = (d.n[0] + txw - 1) / txw;
   d.tiles[1] = (d.n[1] + tyr - 1) / tyr;
-  d.chunk = choose_chunk(D, int64_t(d.tiles[0]) * d.tiles[1], d.n[2]);
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
+    cus = 256;
+  const int bpc = step_blocks_per_cu(D, p.storage, h->wall, h->force);
+  d.chunk = choose_chunk(D, int64_t(d.tiles[0]) * d.tiles[1], d.n[2], int64_t(cus) * bpc);
   d.tiles[2] = (d.n[2] + d.chunk - 1) / d.chunk;
   d.ntiles = int64_t(d.tiles[0]) * d.tiles[1] * d.tiles[2];
   d.tile_base = 0;

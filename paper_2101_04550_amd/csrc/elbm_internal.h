@@ -53,6 +53,7 @@ struct alignas(16) LatticeDesc {
   float inv_lam[3];
   float inv_lam2[3];
   float half_inv_lam[3];   // 1 / (2 lambda): central-difference factor
+  float mfac[3];           // lambda / scale: stored-value sums -> momentum deviation
   float anom[3];           // lambda^2 - 3T: linear coefficient of the anomaly
   float uref[3];           // reference velocity of the stored deviations
   float W[3][3];           // reference triplets Psi_c(uref, T + uref^2, lambda), c = -1, 0, 1
@@ -61,6 +62,8 @@ struct alignas(16) LatticeDesc {
   float T;
   float omega;
   float coef;              // (2 - omega)/(2 omega); 0 for the uncorrected control
+  float om1;               // 1 - omega
+  float oms;               // omega * scale
   float inv_scale;         // stored value * inv_scale = deviation
   float scale;
   float pad1;
@@ -96,6 +99,8 @@ struct LatticeConst64 {
 hipError_t launch_step(int D, int storage, bool wall, bool force, const TableHeader* hdr,
                        const LatticeDesc* table, int64_t substep, int grid, hipStream_t st);
 int step_block_threads(int D);
+// Resident step blocks per compute unit for a kernel class (occupancy query).
+int step_blocks_per_cu(int D, int storage, bool wall, bool force);
 
 hipError_t launch_init(const LatticeConst64& c, const double* stage, int64_t cell0, int64_t count,
                        void* dst, hipStream_t st);

@@ -48,29 +48,46 @@
 namespace elbm {
 namespace {
 
+// Storage formats through their raw bits: FP32 values, or the 16 bits of an
+// FP16 / BF16 value (deviations scaled by the lattice's storage scale).
+// Stores bypass cache allocation: a step's output is not read again until the
+// next launch.
 template <int S>
 struct Store;
 
 template <>
 struct Store<0> {
   using T = float;
-  __device__ static __forceinline__ float load(const T* p) { return *p; }
-  __device__ static __forceinline__ void store(T* p, float v) { *p = v; }
+  using R = float;
+  __device__ static __forceinline__ R load_raw(const T* p) { return *p; }
+  __device__ static __forceinline__ float to_float(R r) { return r; }
+  __device__ static __forceinline__ void store(T* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 
 template <>
 struct Store<1> {
   using T = __half;
-  __device__ static __forceinline__ float load(const T* p) { return __half2float(*p); }
-  __device__ static __forceinline__ void store(T* p, float v) { *p = __float2half_rn(v); }
+  using R = unsigned short;
+  __device__ static __forceinline__ R load_raw(const T* p) { return *reinterpret_cast<const R*>(p); }
+  __device__ static __forceinline__ float to_float(R r) { return __half2float(__ushort_as_half(r)); }
+  __device__ static __forceinline__ void store(T* p, float v) {
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)), reinterpret_cast<R*>(p));
+  }
 };
 
 template <>
 struct Store<2> {
   using T = __hip_bfloat16;
-  __device__ static __forceinline__ float load(const T* p) { return __bfloat162float(*p); }
-  __device__ static __forceinline__ void store(T* p, float v) { *p = __float2bfloat16(v); }
+  using R = unsigned short;
+  __device__ static __forceinline__ R load_raw(const T* p) { return *reinterpret_cast<const R*>(p); }
+  __device__ static __forceinline__ float to_float(R r) { return __uint_as_float(unsigned(r) << 16); }
+  __device__ static __forceinline__ void store(T* p, float v) {
+    __builtin_nontemporal_store(__bfloat16_as_ushort(__float2bfloat16(v)), reinterpret_cast<R*>(p));
+  }
 };
+
+// 1/x with the hardware reciprocal (1 ulp).
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Velocity component of direction i along an internal axis. Directions are
 // numbered lexicographically over the lattice's own axes:
@@ -107,9 +124,17 @@ struct TileConst {
   int n0, n1, n2, plane;
   int64_t stride;
   bool w0, w1, w2;
-  float lam[3], inv_lam[3], inv_lam2[3], hil[3], anom[3], uref[3], g[3];
+  float lam[3], inv_lam[3], inv_lam2[3], hil[3], mfac[3], anom[3], uref[3], g[3];
   float W[3][3], WW[3][3];
-  float omega, coef, inv_scale, scale;
+  float omega, coef, inv_scale, scale, om1, oms;
+};
+
+// Pulled populations of one node in storage format (FP32 value, or the raw
+// 16 bits of an FP16 / BF16 value).
+template <int S, int Q>
+struct Pops {
+  typename Store<S>::R v[Q];
+  __device__ __forceinline__ float get(int i) const { return Store<S>::to_float(v[i]); }
 };
 
 template <int D, int S, bool WALL>
@@ -117,12 +142,12 @@ struct Puller {
   using T = typename Store<S>::T;
   static constexpr int Q = Geo<D, S>::Q;
 
-  // Pulls the populations arriving at node (x, y, z) (all in range) and
-  // accumulates the deviation moments drho = sum h, dj_a = lambda_a sum c_ia h.
-  // With KEEP the pulled deviations are kept in h.
+  // Pulls the populations arriving at node (x, y, z) (all in range) and forms
+  // the deviation moments drho = sum h, dj_a = lambda_a sum c_ia h. With KEEP
+  // the pulled values are kept (in storage format) in h.
   template <bool KEEP>
   __device__ static __forceinline__ void pull(const TileConst& k, const T* __restrict__ src, int x,
-                                              int y, int z, float (&h)[Q], float& drho, float (&dj)[3]) {
+                                              int y, int z, Pops<S, Q>& h, float& drho, float (&dj)[3]) {
     int sx[3], sy[3], sz[3];
     bool ox[3], oy[3], oz[3];
 #pragma unroll
@@ -136,30 +161,65 @@ struct Puller {
       sz[c] = wrap(az, k.n2) * k.plane;
     }
     const int own = x + k.n0 * (y + k.n1 * z);
-    float r = 0.f, j0 = 0.f, j1 = 0.f, j2 = 0.f;
+    float v[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int c0 = cq<D>(i, 0), c1 = cq<D>(i, 1), c2 = cq<D>(i, 2);
       const int o = sx[c0 + 1] + sy[c1 + 1] + sz[c2 + 1];
-      float v = Store<S>::load(src + i * k.stride + o);
+      auto raw = Store<S>::load_raw(src + i * k.stride + o);
       if (WALL) {
         const bool out = (c0 != 0 && ox[c0 + 1]) || (c1 != 0 && oy[c1 + 1]) || (c2 != 0 && oz[c2 + 1]);
-        if (out) v = Store<S>::load(src + (Q - 1 - i) * k.stride + own);
+        if (out) raw = Store<S>::load_raw(src + (Q - 1 - i) * k.stride + own);
       }
-      if (S != 0) v *= k.inv_scale;
-      if (KEEP) h[i] = v;
-      r += v;
-      if (c0 > 0) j0 += v;
-      if (c0 < 0) j0 -= v;
-      if (c1 > 0) j1 += v;
-      if (c1 < 0) j1 -= v;
-      if (c2 > 0) j2 += v;
-      if (c2 < 0) j2 -= v;
+      if (KEEP) h.v[i] = raw;
+      v[i] = Store<S>::to_float(raw);
     }
-    drho = r;
-    dj[0] = k.lam[0] * j0;
-    dj[1] = k.lam[1] * j1;
-    dj[2] = k.lam[2] * j2;
+    float r, m[3];
+    line_moments(v, r, m);
+    // values are in storage scale: the factors carry 1/scale
+    drho = r * k.inv_scale;
+    dj[0] = k.mfac[0] * m[0];
+    dj[1] = k.mfac[1] * m[1];
+    dj[2] = k.mfac[2] * m[2];
+  }
+
+  // Moments of the 3^D values in lattice order: sums along x-lines of three
+  // first, then combined (fewer additions than direction by direction).
+  __device__ static __forceinline__ void line_moments(const float (&v)[Q], float& r, float (&m)[3]) {
+    if (D == 3) {
+      float s[3][3], jx = 0.f;
+#pragma unroll
+      for (int k2 = 0; k2 < 3; ++k2)
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) {
+          const int b = 3 * k1 + 9 * k2;
+          s[k1][k2] = (v[b] + v[b + 1]) + v[b + 2];
+          jx += v[b + 2] - v[b];
+        }
+      float rr = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+      for (int k2 = 0; k2 < 3; ++k2) rr += (s[0][k2] + s[1][k2]) + s[2][k2];
+#pragma unroll
+      for (int k2 = 0; k2 < 3; ++k2) jy += s[2][k2] - s[0][k2];
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) jz += s[k1][2] - s[k1][0];
+      r = rr;
+      m[0] = jx;
+      m[1] = jy;
+      m[2] = jz;
+    } else {
+      float s[3], jx = 0.f;
+#pragma unroll
+      for (int k2 = 0; k2 < 3; ++k2) {
+        const int b = 3 * k2;
+        s[k2] = (v[b] + v[b + 1]) + v[b + 2];
+        jx += v[b + 2] - v[b];
+      }
+      r = (s[0] + s[1]) + s[2];
+      m[0] = jx;
+      m[1] = 0.f;
+      m[2] = s[2] - s[0];
+    }
   }
 };
 
@@ -193,6 +253,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     k.inv_lam[a] = Ld->inv_lam[a];
     k.inv_lam2[a] = Ld->inv_lam2[a];
     k.hil[a] = Ld->half_inv_lam[a];
+    k.mfac[a] = Ld->mfac[a];
     k.anom[a] = Ld->anom[a];
     k.uref[a] = Ld->uref[a];
     k.g[a] = Ld->g[a];
@@ -206,6 +267,8 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   k.coef = Ld->coef;
   k.inv_scale = Ld->inv_scale;
   k.scale = Ld->scale;
+  k.om1 = Ld->om1;
+  k.oms = Ld->oms;
   const T* __restrict__ src = static_cast<const T*>(Ld->buf[parity]);
   T* __restrict__ dst = static_cast<T*>(Ld->buf[parity ^ 1]);
 
@@ -288,9 +351,10 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   const float h_anom = hax == 0 ? k.anom[0] : k.anom[1];
   auto halo = [&](int z, int b) {
     if (has_halo) {
-      float dr, dj[3], unused[Q];
+      float dr, dj[3];
+      Pops<S, Q> unused;
       P::template pull<false>(k, src, hx, hy, z, unused, dr, dj);
-      const float ir = 1.f / (1.f + dr);
+      const float ir = recip(1.f + dr);
       const float j = h_uref + (hax == 0 ? dj[0] : dj[1]);
       const float u = j * ir;
       hbase[b * hstep + hslot] = j * h_anom - j * u * u;
@@ -300,7 +364,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   const int cx = active ? gx : 0, cy = active ? gy : 0;
 
   // ---- prologue: plane before the chunk (ring) and the first plane ----
-  float h[Q], hn[Q];
+  Pops<S, Q> h, hn;
   float drho = 0.f, dj[3] = {0.f, 0.f, 0.f};
   float qc[3] = {0.f, 0.f, 0.f};  // anomaly of the current plane at this node
   float qprev = 0.f;
@@ -311,11 +375,11 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     if (active && !ghost_prev) {
       float dr, djp[3];
       P::template pull<false>(k, src, cx, cy, zp, hn, dr, djp);
-      qprev = anomaly(k, 2, djp[2], 1.f / (1.f + dr));
+      qprev = anomaly(k, 2, djp[2], recip(1.f + dr));
     }
     if (active) {
       P::template pull<true>(k, src, cx, cy, z0, h, drho, dj);
-      const float ir = 1.f / (1.f + drho);
+      const float ir = recip(1.f + drho);
       qc[0] = anomaly(k, 0, dj[0], ir);
       if (D == 3) qc[1] = anomaly(k, 1, dj[1], ir);
       qc[2] = anomaly(k, 2, dj[2], ir);
@@ -337,7 +401,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     const bool more = z + 1 < z1;
     if (active && !ghost_next) {
       P::template pull<true>(k, src, cx, cy, zn, hn, drn, djn);
-      const float ir = 1.f / (1.f + drn);
+      const float ir = recip(1.f + drn);
       qn[0] = anomaly(k, 0, djn[0], ir);
       if (D == 3) qn[1] = anomaly(k, 1, djn[1], ir);
       qn[2] = anomaly(k, 2, djn[2], ir);
@@ -362,7 +426,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       Gd[2] = (qnext - qprev) * k.hil[2];
 
       const float rho = 1.f + drho;
-      const float ir = 1.f / rho;
+      const float ir = recip(rho);
       float du[3], dP[3], d[3][3], p[3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -425,9 +489,10 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
           hs = drho * X + dX;
           if (FORCE) fr = rho * (e[0][c0] * (pe[2][c2] + e[2][c2]) + pe[0][c0] * e[2][c2]);
         }
-        float o = h[i] + k.omega * (hs - h[i]);
-        if (FORCE) o += fr;
-        if (S != 0) o *= k.scale;
+        // relaxation (Sec. 2.1, eq. LBGK) in storage scale:
+        // o = (1 - w) h + w scale f* (+ scale F)
+        float o = k.om1 * h.get(i) + k.oms * hs;
+        if (FORCE) o += k.scale * fr;
         Store<S>::store(dst + i * k.stride + own, o);
       }
     }
@@ -437,8 +502,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       if (D == 3) qyb[b ^ 1][sy_own] = qn[1];
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < Q; ++i) h[i] = hn[i];
+    h = hn;
     drho = drn;
     dj[0] = djn[0];
     dj[1] = djn[1];
@@ -496,6 +560,36 @@ hipError_t launch_ds(bool wall, bool force, const TableHeader* hdr, const Lattic
 }  // namespace
 
 int step_block_threads(int D) { return D == 3 ? Geo<3, 0>::NT : Geo<2, 0>::NT; }
+
+template <int D, int S, bool WALL, bool FORCE>
+int occupancy_one() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<D, S, WALL, FORCE>, Geo<D, S>::NT, 0) !=
+      hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+template <int D, int S>
+int occupancy_ds(bool wall, bool force) {
+  if (wall) return force ? occupancy_one<D, S, true, true>() : occupancy_one<D, S, true, false>();
+  return force ? occupancy_one<D, S, false, true>() : occupancy_one<D, S, false, false>();
+}
+
+int step_blocks_per_cu(int D, int storage, bool wall, bool force) {
+  if (D == 3) {
+    switch (storage) {
+      case 0: return occupancy_ds<3, 0>(wall, force);
+      case 1: return occupancy_ds<3, 1>(wall, force);
+      default: return occupancy_ds<3, 2>(wall, force);
+    }
+  }
+  switch (storage) {
+    case 0: return occupancy_ds<2, 0>(wall, force);
+    case 1: return occupancy_ds<2, 1>(wall, force);
+    default: return occupancy_ds<2, 2>(wall, force);
+  }
+}
 
 hipError_t launch_step(int D, int storage, bool wall, bool force, const TableHeader* hdr,
                        const LatticeDesc* table, int64_t substep, int grid, hipStream_t st) {
