@@ -49,6 +49,8 @@ def parse_args():
     ap.add_argument("--kernel-reps", type=int, default=200, help="step launches timed for the roofline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the served mixed stream (0: skip the serving leg)")
     return ap.parse_args()
 
 
@@ -148,6 +150,26 @@ def run_gpu(storage, fld, steps, warmup, kernel_reps):
         "enstrophy_last": hist[-1]["enstrophy"] if hist else None,
         "final_min_rho": d["min_rho"],
     }
+
+
+def serving_leg(nreq):
+    """Continuous batching of the seeded mixed stream: Poisson arrivals at
+    50 req/s, 10% D3Q27 turbulence boxes (64^3..192^3), the rest D2Q9 shear
+    waves and double shear layers (64^2..1024^2), cubic or stretched, T in
+    {1/3, 1/2}, 200..5000 steps, FP32 / FP16 storage."""
+    import torch
+
+    from paper_2101_04550_amd import serving as SV
+
+    reqs = SV.attach_fields(SV.make_stream(nreq, rate=50.0, share_3d=0.1))
+    srv = SV.Server(64 * 2 ** 30, max_slots=64, quantum=100, use_graph=True)
+    res = srv.run(reqs)
+    out = SV.summarize(res, srv.makespan)
+    out.update({"arrival_rate_per_s": 50.0, "share_3d": 0.1, "quantum_steps": 100, "rounds": srv.rounds,
+                "peak_slots": srv.peak_slots, "pool_gb": 64})
+    srv.close()
+    torch.cuda.empty_cache()
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
 
 
 def cpu_baseline(seconds_budget=20.0):
@@ -255,6 +277,10 @@ def main():
                             "enstrophy_last": r["enstrophy_last"], "min_rho": r["final_min_rho"]}
                         for s, r in runs.items()},
     }
+    if args.serve_requests > 0 and args.n == N_HIT:
+        out["serving"] = serving_leg(args.serve_requests)
+        print(f"# serving: {out['serving']['solves_per_s']:.1f} solves/s, p50 {out['serving']['p50_latency_s']:.3f} s, "
+              f"p99 {out['serving']['p99_latency_s']:.3f} s", file=sys.stderr, flush=True)
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
