@@ -90,7 +90,8 @@ class _Active:
 class Server:
     """Admission by device footprint, resident lattices, graph-replayed fused rounds."""
 
-    def __init__(self, pool_bytes: int, max_slots: int = 64, quantum: int = 100, use_graph: bool = True):
+    def __init__(self, pool_bytes: int, max_slots: int = 64, quantum: int = 100, use_graph: bool = True,
+                 checksums: bool = False):
         import torch
 
         self.torch = torch
@@ -98,6 +99,7 @@ class Server:
         self.max_slots = int(max_slots)
         self.quantum = int(quantum)
         self.use_graph = bool(use_graph)
+        self.checksums = bool(checksums)
         self.batch = E.Batch(self.max_slots)
         self.used = 0
         self.rounds = 0
@@ -120,7 +122,11 @@ class Server:
         return nactive < self.max_slots and self.used + E.query_bytes(req.params()) <= self.pool_bytes
 
     def run(self, requests, clock=time.perf_counter):
-        """Serves `requests` (arrival times in seconds from the start); returns results by rid."""
+        """Serves `requests` (arrival times in seconds from the start); returns results by rid.
+
+        Each round launches one batched run of up to `quantum` steps for every
+        resident lattice; while the GPU works, newly arrived requests are
+        admitted (their fields uploaded) and join the next round."""
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         for r in pending:
             if E.query_bytes(r.params()) > self.pool_bytes:
@@ -129,13 +135,18 @@ class Server:
         active = []
         results = {}
         t0 = clock()
-        while pending or waiting or active:
+
+        def admit_arrived(nresident):
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
-            # admit in arrival order while memory and slots allow
-            while waiting and self.fits(waiting[0], len(active)):
-                active.append(self._admit(waiting.popleft(), clock() - t0))
+            joined = []
+            while waiting and self.fits(waiting[0], nresident + len(joined)):
+                joined.append(self._admit(waiting.popleft(), clock() - t0))
+            return joined
+
+        while pending or waiting or active:
+            active += admit_arrived(len(active))
             self.peak_slots = max(self.peak_slots, len(active))
             if not active:
                 if pending:
@@ -144,6 +155,8 @@ class Server:
             steps = [min(self.quantum, a.remaining) for a in active]
             self.batch.run([a.lat for a in active], steps, use_graph=self.use_graph)
             self.rounds += 1
+            # overlap: admit arrivals while the round runs (they join the next round)
+            joined = admit_arrived(len(active))
             self.torch.cuda.synchronize()
             done_at = clock() - t0
             still = []
@@ -153,12 +166,13 @@ class Server:
                     still.append(a)
                     continue
                 d = a.lat.diag(check=False)
+                cs = state_checksum(a.lat) if self.checksums else ""
                 results[a.req.rid] = Result(a.req.rid, a.req.arrival, a.admitted, done_at, a.req.steps,
-                                            a.req.cells, d["ke"], d["enstrophy"], d["min_rho"],
-                                            state_checksum(a.lat))
+                                            a.req.cells, d["ke"], d["enstrophy"], d["min_rho"], cs)
                 a.lat.close()
                 self.used -= a.nbytes
-            active = still
+            active = still + joined
+            self.peak_slots = max(self.peak_slots, len(active))
         self.makespan = clock() - t0
         return results
 

@@ -59,7 +59,7 @@ def test_served_results_equal_solo_under_queueing(use_graph):
     reqs = small_stream()
     sizes = [E.query_bytes(r.params()) for r in reqs]
     budget = 3 * max(sizes)  # only a few lattices fit at once: later arrivals queue
-    srv = SV.Server(budget, max_slots=4, quantum=37, use_graph=use_graph)
+    srv = SV.Server(budget, max_slots=4, quantum=37, use_graph=use_graph, checksums=True)
     res = srv.run(reqs)
     srv.close()
     assert sorted(res) == [r.rid for r in reqs]
