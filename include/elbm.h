@@ -142,13 +142,17 @@ const char* elbm_last_error(void);
 
 /* Checks a parameter set without touching the GPU (Sec. 2.1: omega in (0,2),
  * T > 0; Sec. 2.2: lambda > 0, rest-population weight 1 - T/lambda^2 > 0 on
- * every axis; at least 3 nodes on a periodic axis, 2 on a wall axis).
+ * every axis; at least 3 nodes on a periodic axis, 2 on a wall axis; at most
+ * 2^31 - 1 nodes, and Q times the nodes of one plane across the slowest axis
+ * (n_x n_y for D3Q27, n_x for D2Q9) times the element size below 2^32 bytes).
  * Returns ELBM_EINVAL or ELBM_EUNSUPPORTED with a message, else ELBM_OK. */
 int32_t elbm_validate(const elbm_params* params);
 
-/* Device bytes a lattice needs: two population buffers (ping-pong) of
- * Q * stride * sizeof(storage) bytes each plus a small fixed scratch area
- * (descriptor, diagnostic partial sums, history). Pure host arithmetic. */
+/* Device bytes a lattice needs: two population buffers (ping-pong) of about
+ * Q * N * sizeof(storage) bytes each (stored plane by plane along the slowest
+ * axis, each direction's array of a plane padded to 64 elements) plus a small
+ * fixed scratch area (descriptor, diagnostic partial sums, history). Pure
+ * host arithmetic. */
 int32_t elbm_query_bytes(const elbm_params* params, size_t* bytes);
 
 /* Creates a lattice in the caller's device buffer `dev_buf` of `bytes`

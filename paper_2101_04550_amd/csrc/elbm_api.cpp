@@ -23,7 +23,7 @@ using namespace elbm;
 struct elbm_lattice {
   elbm_params p;
   int D = 0, Q = 0, device = 0;
-  int64_t N = 0, stride = 0;
+  int64_t N = 0, pstride = 0, plane = 0, nplanes = 0;
   size_t es = 4, pop_bytes = 0;
   char* base = nullptr;
   void* buf[2] = {nullptr, nullptr};
@@ -95,7 +95,7 @@ double psi(int c, double u, double P, double lam) {
 
 struct Layout {
   int D = 0, Q = 0;
-  int64_t N = 0, stride = 0;
+  int64_t N = 0, pstride = 0, plane = 0, nplanes = 0;
   size_t es = 4, pop_bytes = 0;
   size_t off_buf[2] = {0, 0};
   size_t off_hdr = 0, off_desc = 0, off_partials = 0, off_hist = 0, off_last = 0, off_count = 0, total = 0;
@@ -133,7 +133,15 @@ int32_t check(const elbm_params* p) {
     if (N > std::numeric_limits<int32_t>::max())
       return fail(ELBM_EINVAL, "too many nodes: at most 2^31 - 1 per lattice");
   }
-  if (p->n[0] * p->n[1] >= (int64_t(1) << 30)) return fail(ELBM_EINVAL, "n_x * n_y must stay below 2^30");
+  {
+    // one plane slab of the marched axis (Q padded direction arrays) must be
+    // addressable with 32-bit byte offsets
+    const int64_t plane = D == 3 ? p->n[0] * p->n[1] : p->n[0];
+    const int64_t es = p->storage == ELBM_STORE_F32 ? 4 : 2;
+    if ((plane + 64) * p->lattice * es >= (int64_t(1) << 32))
+      return fail(ELBM_EINVAL, "too many nodes per plane: Q * n_x * n_y (D3Q27) or Q * n_x (D2Q9) times the element "
+                               "size must stay below 2^32 bytes");
+  }
   if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(ELBM_EINVAL, "T must be positive and finite");
   if (!(p->omega > 0.0 && p->omega < 2.0)) return fail(ELBM_EINVAL, "omega must lie in (0, 2)");
   for (int a = 0; a < D; ++a) {
@@ -157,8 +165,11 @@ Layout layout_of(const elbm_params* p) {
   L.Q = p->lattice;
   L.N = p->n[0] * p->n[1] * p->n[2];
   L.es = p->storage == ELBM_STORE_F32 ? 4 : 2;
-  L.stride = int64_t(align_up(size_t(L.N), 256)) + stride_pad();
-  L.pop_bytes = align_up(size_t(L.Q) * size_t(L.stride) * L.es, 4096);
+  L.plane = L.D == 3 ? int64_t(p->n[0]) * p->n[1] : p->n[0];
+  L.nplanes = L.D == 3 ? p->n[2] : p->n[1];
+  L.pstride = int64_t(align_up(size_t(L.plane), 64)) + stride_pad();
+  // (a small tail keeps vector loads near the end of the last slab in range)
+  L.pop_bytes = align_up(size_t(L.nplanes) * size_t(L.Q) * size_t(L.pstride) * L.es + 1024, 4096);
   L.capacity = p->diag_every > 0 ? p->diag_capacity : 0;
   size_t o = 0;
   L.off_buf[0] = o;
@@ -247,7 +258,7 @@ void fill_desc(elbm_lattice* h) {
   d.inv_scale = float(1.0 / scale);
   d.buf[0] = h->buf[0];
   d.buf[1] = h->buf[1];
-  d.stride = h->stride;
+  d.pstride = h->pstride;
   const int txw = D == 3 ? kTileX3 : 64 * kStrips2;
   const int tyr = D == 3 ? kRows3 : 1;
   d.tiles[0] = (d.n[0] + txw - 1) / txw;
@@ -270,7 +281,8 @@ void fill_desc(elbm_lattice* h) {
   c.D = D;
   c.Q = h->Q;
   c.N = h->N;
-  c.stride = h->stride;
+  c.pstride = h->pstride;
+  c.plane = h->plane;
   c.storage = p.storage;
   c.T = p.T;
   c.scale = scale;
@@ -331,12 +343,15 @@ void record_to_diag(const double* r, elbm_diag_record* out) {
   out->nan_count = int64_t(r[R_NAN]);
 }
 
+// Checkpoint: this header, then the raw plane-slab state.
+constexpr char kCkptMagic[9] = "ELBMCKP2";
+
 struct CkptHeader {
   char magic[8];
   uint32_t abi;
   uint32_t es;
   int64_t step;
-  int64_t stride;
+  int64_t pstride;
   int64_t bytes;
   elbm_params params;
 };
@@ -395,7 +410,9 @@ int32_t elbm_create(const elbm_params* p, void* dev_buf, size_t bytes, void* hip
   h->D = L.D;
   h->Q = L.Q;
   h->N = L.N;
-  h->stride = L.stride;
+  h->pstride = L.pstride;
+  h->plane = L.plane;
+  h->nplanes = L.nplanes;
   h->es = L.es;
   h->pop_bytes = L.pop_bytes;
   h->base = static_cast<char*>(dev_buf);
@@ -424,6 +441,10 @@ int32_t elbm_create(const elbm_params* p, void* dev_buf, size_t bytes, void* hip
   e = hipMemcpyAsync(h->hdr_dev, &hdr, sizeof hdr, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(h->desc_dev, &h->desc, sizeof h->desc, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->hist_count, 0, sizeof(int64_t), h->stream);
+  // The padding of the direction arrays is never written by the kernels; it
+  // starts (and stays) zero so that saved states are byte-identical whenever
+  // the populations are.
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMemsetAsync(h->buf[b], 0, h->pop_bytes, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     (void)hipEventDestroy(h->event);
@@ -450,6 +471,8 @@ int32_t elbm_init(elbm_handle h, const double* rho, const double* u) {
                             h->stream));
     HIPCHK(launch_init(h->c64, stage, c0, cnt, h->buf[0], h->stream));
   }
+  // the staging area was the other buffer: return it to zero (see elbm_create)
+  HIPCHK(hipMemsetAsync(h->buf[1], 0, h->pop_bytes, h->stream));
   s = reset_history(h);
   if (s) return s;
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -555,7 +578,7 @@ int32_t elbm_diag_history(elbm_handle h, elbm_diag_record* out, int32_t max, int
 
 int32_t elbm_checkpoint_bytes(elbm_handle h, size_t* bytes) {
   if (!h || !bytes) return fail(ELBM_EINVAL, "NULL argument");
-  *bytes = sizeof(CkptHeader) + size_t(h->Q) * size_t(h->stride) * h->es;
+  *bytes = sizeof(CkptHeader) + size_t(h->nplanes) * size_t(h->Q) * size_t(h->pstride) * h->es;
   return ELBM_OK;
 }
 
@@ -567,11 +590,11 @@ int32_t elbm_save(elbm_handle h, void* host, size_t bytes) {
   int32_t s = set_dev(h->device);
   if (s) return s;
   CkptHeader hd{};
-  std::memcpy(hd.magic, "ELBMCKP1", 8);
+  std::memcpy(hd.magic, kCkptMagic, 8);
   hd.abi = ELBM_ABI_VERSION;
   hd.es = uint32_t(h->es);
   hd.step = h->step;
-  hd.stride = h->stride;
+  hd.pstride = h->pstride;
   hd.bytes = int64_t(need);
   hd.params = h->p;
   std::memcpy(host, &hd, sizeof hd);
@@ -588,8 +611,8 @@ int32_t elbm_load(elbm_handle h, const void* host, size_t bytes) {
   if (bytes < need) return fail(ELBM_EINVAL, "checkpoint buffer too small");
   CkptHeader hd;
   std::memcpy(&hd, host, sizeof hd);
-  if (std::memcmp(hd.magic, "ELBMCKP1", 8) != 0 || hd.abi != ELBM_ABI_VERSION || hd.es != h->es ||
-      hd.stride != h->stride || hd.bytes != int64_t(need) || !same_problem(hd.params, h->p) || hd.step < 0)
+  if (std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.abi != ELBM_ABI_VERSION || hd.es != h->es ||
+      hd.pstride != h->pstride || hd.bytes != int64_t(need) || !same_problem(hd.params, h->p) || hd.step < 0)
     return fail(ELBM_EINVAL, "checkpoint does not match this lattice");
   int32_t s = set_dev(h->device);
   if (s) return s;

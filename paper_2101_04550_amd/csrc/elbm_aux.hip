@@ -67,6 +67,13 @@ __device__ __forceinline__ double psi(int ci, double u, double P, double lam) {
   return 0.5 * (ci * u / lam + P / (lam * lam));
 }
 
+// Element index of population 0 of node `cell` (x fastest over the lattice)
+// in the plane-slab layout; population i is pstride elements further on.
+__device__ __forceinline__ int64_t slab_base(const LatticeConst64& c, int64_t cell) {
+  const uint32_t z = uint32_t(cell) / uint32_t(c.plane);
+  return int64_t(z) * c.Q * c.pstride + (cell - int64_t(z) * c.plane);
+}
+
 template <int S>
 __global__ void init_kernel(LatticeConst64 c, const double* __restrict__ stage, int64_t cell0, int64_t count,
                             void* __restrict__ dstv) {
@@ -80,7 +87,7 @@ __global__ void init_kernel(LatticeConst64 c, const double* __restrict__ stage, 
       u[a] = stage[(1 + a) * count + k] + c.uref[a];
       P[a] = c.T + u[a] * u[a];  // equilibrium pressure (Sec. 2.3, eq. Peqa)
     }
-    const int64_t cell = cell0 + k;
+    const int64_t base = slab_base(c, cell0 + k);
     for (int i = 0; i < c.Q; ++i) {
       double f = rho, w = 1.0;
       for (int a = 0; a < c.D; ++a) {
@@ -88,7 +95,7 @@ __global__ void init_kernel(LatticeConst64 c, const double* __restrict__ stage, 
         f *= psi(ci, u[a], P[a], c.lam[a]);
         w *= c.W[a][ci + 1];
       }
-      Raw<S>::put(dst + i * c.stride + cell, (f - w) * c.scale);
+      Raw<S>::put(dst + base + i * c.pstride, (f - w) * c.scale);
     }
   }
 }
@@ -96,19 +103,19 @@ __global__ void init_kernel(LatticeConst64 c, const double* __restrict__ stage, 
 template <int S>
 __global__ void pop_out_kernel(LatticeConst64 c, const void* __restrict__ srcv, int i, double* __restrict__ out) {
   using T = typename Raw<S>::T;
-  const T* src = static_cast<const T*>(srcv) + i * c.stride;
+  const T* src = static_cast<const T*>(srcv) + i * c.pstride;
   const double w = ref_weight(c, i);
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < c.N; k += int64_t(gridDim.x) * blockDim.x)
-    out[k] = w + Raw<S>::get(src + k) * c.inv_scale;
+    out[k] = w + Raw<S>::get(src + slab_base(c, k)) * c.inv_scale;
 }
 
 template <int S>
 __global__ void pop_in_kernel(LatticeConst64 c, const double* __restrict__ in, int i, void* __restrict__ dstv) {
   using T = typename Raw<S>::T;
-  T* dst = static_cast<T*>(dstv) + i * c.stride;
+  T* dst = static_cast<T*>(dstv) + i * c.pstride;
   const double w = ref_weight(c, i);
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < c.N; k += int64_t(gridDim.x) * blockDim.x)
-    Raw<S>::put(dst + k, (in[k] - w) * c.scale);
+    Raw<S>::put(dst + slab_base(c, k), (in[k] - w) * c.scale);
 }
 
 // FP64 moments of one node of the stored state: rho and the reported
@@ -118,8 +125,9 @@ __device__ __forceinline__ void node_moments(const LatticeConst64& c, const type
                                              double& rho, double (&u)[3]) {
   constexpr int Q = D == 3 ? 27 : 9;
   double h[Q];
+  const int64_t base = slab_base(c, cell);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) h[i] = Raw<S>::get(src + i * c.stride + cell);
+  for (int i = 0; i < Q; ++i) h[i] = Raw<S>::get(src + base + i * c.pstride);
   double dr = 0.0, dj[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {

@@ -1,13 +1,21 @@
 // Internal declarations shared by the HIP kernels and the C-ABI host code.
 //
-// Axis roles inside the kernels. A lattice is stored as Q structure-of-arrays
-// population arrays, x fastest. The kernels see three internal axes:
+// Axis roles inside the kernels. The kernels see three internal axes:
 //   axis 0 -- x, the fastest (coalesced) axis, tiled in 64-wide wavefronts;
 //   axis 1 -- the tiled row axis (y for D3Q27; absent, extent 1, for D2Q9);
 //   axis 2 -- the marched axis, walked plane by plane with a register ring
 //             (z for D3Q27; y for D2Q9).
 // So a D2Q9 lattice n_x x n_y is handled as internal extents (n_x, 1, n_y)
-// with velocity components (c_x, 0, c_y); memory order is unchanged.
+// with velocity components (c_x, 0, c_y).
+//
+// Population layout ("plane slabs"). The state is stored plane by plane along
+// the marched axis: plane z holds Q arrays, one per direction, each covering
+// the plane's n_0 n_1 nodes x fastest and padded to `pstride` elements; so
+// population i of the node with in-plane index p on plane z sits at element
+//   z * Q * pstride + i * pstride + p.
+// Every offset inside one slab (Q pstride elements) stays below 2^32 bytes, so
+// the step kernel addresses a slab through one buffer resource with 32-bit
+// offsets, whatever the size of the whole lattice.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,7 +47,7 @@ enum RecField {
 // advance one tile of one lattice. Plain data, copied host -> device.
 struct alignas(16) LatticeDesc {
   void* buf[2];            // population buffers; state of substep s is in buf[(parity0 + s) & 1]
-  int64_t stride;          // elements between consecutive population arrays
+  int64_t pstride;         // elements between consecutive direction arrays of a plane slab
   int64_t tile_base;       // first global tile index of this lattice in its table
   int64_t ntiles;          // tiles of this lattice
   int64_t nsteps;          // substeps this lattice takes part in (s < nsteps)
@@ -81,7 +89,8 @@ struct LatticeConst64 {
   int32_t D, Q;
   int32_t n[3];            // physical extents (x, y, z), z = 1 for D2Q9
   int32_t wall[3];         // physical axes
-  int64_t stride;
+  int64_t pstride;         // elements between direction arrays of a plane slab
+  int64_t plane;           // nodes per plane of the marched axis (n_x n_y; n_x for D2Q9)
   int64_t N;
   double lam[3];           // physical axes
   double T;

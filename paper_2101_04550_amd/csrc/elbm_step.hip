@@ -48,10 +48,18 @@
 namespace elbm {
 namespace {
 
+// Population arrays are accessed through buffer resources: a uniform base
+// address (direction and plane, in scalar registers) plus a 32-bit per-lane
+// byte offset that stays fixed along the march. Bounds checking is left open
+// (num_records = 2^32 - 1); every offset is in range by construction.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc rsrc(const char* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), 0, -1, 0x00020000);
+}
+constexpr int kNonTemporal = 2;  // cache policy of the stores: no reuse before the next launch
+
 // Storage formats through their raw bits: FP32 values, or the 16 bits of an
 // FP16 / BF16 value (deviations scaled by the lattice's storage scale).
-// Stores bypass cache allocation: a step's output is not read again until the
-// next launch.
 template <int S>
 struct Store;
 
@@ -59,19 +67,25 @@ template <>
 struct Store<0> {
   using T = float;
   using R = float;
-  __device__ static __forceinline__ R load_raw(const T* p) { return *p; }
+  __device__ static __forceinline__ R load(Rsrc r, uint32_t off, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+  }
   __device__ static __forceinline__ float to_float(R r) { return r; }
-  __device__ static __forceinline__ void store(T* p, float v) { __builtin_nontemporal_store(v, p); }
+  __device__ static __forceinline__ void store(Rsrc r, uint32_t off, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, soff, kNonTemporal);
+  }
 };
 
 template <>
 struct Store<1> {
   using T = __half;
   using R = unsigned short;
-  __device__ static __forceinline__ R load_raw(const T* p) { return *reinterpret_cast<const R*>(p); }
+  __device__ static __forceinline__ R load(Rsrc r, uint32_t off, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
+  }
   __device__ static __forceinline__ float to_float(R r) { return __half2float(__ushort_as_half(r)); }
-  __device__ static __forceinline__ void store(T* p, float v) {
-    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)), reinterpret_cast<R*>(p));
+  __device__ static __forceinline__ void store(Rsrc r, uint32_t off, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, off, soff, kNonTemporal);
   }
 };
 
@@ -79,10 +93,12 @@ template <>
 struct Store<2> {
   using T = __hip_bfloat16;
   using R = unsigned short;
-  __device__ static __forceinline__ R load_raw(const T* p) { return *reinterpret_cast<const R*>(p); }
+  __device__ static __forceinline__ R load(Rsrc r, uint32_t off, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
+  }
   __device__ static __forceinline__ float to_float(R r) { return __uint_as_float(unsigned(r) << 16); }
-  __device__ static __forceinline__ void store(T* p, float v) {
-    __builtin_nontemporal_store(__bfloat16_as_ushort(__float2bfloat16(v)), reinterpret_cast<R*>(p));
+  __device__ static __forceinline__ void store(Rsrc r, uint32_t off, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__bfloat16_as_ushort(__float2bfloat16(v)), r, off, soff, kNonTemporal);
   }
 };
 
@@ -121,8 +137,8 @@ __device__ __forceinline__ int wrap(int s, int n) { return s < 0 ? s + n : (s >=
 
 // Per-lattice values a tile needs, copied out of the descriptor once.
 struct TileConst {
-  int n0, n1, n2, plane;
-  int64_t stride;
+  int n0, n1, n2;
+  uint64_t slab_bytes;
   bool w0, w1, w2;
   float lam[3], inv_lam[3], inv_lam2[3], hil[3], mfac[3], anom[3], uref[3], g[3];
   float W[3][3], WW[3][3];
@@ -137,43 +153,77 @@ struct Pops {
   __device__ __forceinline__ float get(int i) const { return Store<S>::to_float(v[i]); }
 };
 
+// Byte offsets, within one plane of the marched axis, of the nodes a node
+// pulls from (x - c_x, y - c_y) and of the node itself; wall flags mark the
+// neighbours that lie beyond a wall. They do not change along the march, so a
+// tile computes them once; the plane and the direction enter as a uniform
+// base address. Planes hold fewer than 2^30 nodes, so FP32 offsets fit 32 bits.
+struct NodeOffs {
+  uint32_t o[3][3];  // [c_x + 1][c_y + 1]
+  uint32_t own;
+  bool ox[3], oy[3];
+};
+
+// Buffer resources of the plane slabs a node of plane z pulls from, z - c_z
+// for c_z = -1, 0, 1 (so r[1] is plane z itself); oz marks source planes beyond
+// a wall. Formed once per plane in uniform control flow and shared by every
+// fetch of that plane.
+struct PlaneSrc {
+  Rsrc r[3];  // [c_z + 1]
+  bool oz[3];
+};
+
 template <int D, int S, bool WALL>
 struct Puller {
   using T = typename Store<S>::T;
+  using R = typename Store<S>::R;
   static constexpr int Q = Geo<D, S>::Q;
 
-  // Pulls the populations arriving at node (x, y, z) (all in range) and forms
-  // the deviation moments drho = sum h, dj_a = lambda_a sum c_ia h. With KEEP
-  // the pulled values are kept (in storage format) in h.
-  template <bool KEEP>
-  __device__ static __forceinline__ void pull(const TileConst& k, const T* __restrict__ src, int x,
-                                              int y, int z, Pops<S, Q>& h, float& drho, float (&dj)[3]) {
-    int sx[3], sy[3], sz[3];
-    bool ox[3], oy[3], oz[3];
+  __device__ static __forceinline__ void offsets(const TileConst& k, int x, int y, NodeOffs& no) {
+    constexpr int sz = sizeof(T);
+    int sx[3], sy[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const int ax = x - (c - 1), ay = y - (c - 1), az = z - (c - 1);
-      ox[c] = WALL && k.w0 && (ax < 0 || ax >= k.n0);
-      oy[c] = WALL && k.w1 && (ay < 0 || ay >= k.n1);
-      oz[c] = WALL && k.w2 && (az < 0 || az >= k.n2);
+      const int ax = x - (c - 1), ay = y - (c - 1);
+      no.ox[c] = WALL && k.w0 && (ax < 0 || ax >= k.n0);
+      no.oy[c] = WALL && k.w1 && (ay < 0 || ay >= k.n1);
       sx[c] = wrap(ax, k.n0);
       sy[c] = (D == 3) ? wrap(ay, k.n1) * k.n0 : 0;
-      sz[c] = wrap(az, k.n2) * k.plane;
     }
-    const int own = x + k.n0 * (y + k.n1 * z);
-    float v[Q];
+#pragma unroll
+    for (int c0 = 0; c0 < 3; ++c0)
+#pragma unroll
+      for (int c1 = 0; c1 < 3; ++c1) no.o[c0][c1] = uint32_t(sx[c0] + sy[c1]) * sz;
+    no.own = uint32_t(x + k.n0 * y) * sz;
+  }
+
+  // Issues the loads of the populations arriving at a node of marched plane z
+  // from the planes z - c_z; the values land in h in storage format. `sb` is
+  // the byte distance of consecutive direction arrays in a slab. Where `near`
+  // (uniform: the tile or the plane touches a wall) the halfway bounce-back
+  // applies: a population that would arrive from beyond a wall is the node's
+  // own post-collision population of the opposite direction.
+  __device__ static __forceinline__ void fetch(uint32_t sb, const PlaneSrc& ps, const NodeOffs& no, bool near,
+                                               Pops<S, Q>& h) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int c0 = cq<D>(i, 0), c1 = cq<D>(i, 1), c2 = cq<D>(i, 2);
-      const int o = sx[c0 + 1] + sy[c1 + 1] + sz[c2 + 1];
-      auto raw = Store<S>::load_raw(src + i * k.stride + o);
-      if (WALL) {
-        const bool out = (c0 != 0 && ox[c0 + 1]) || (c1 != 0 && oy[c1 + 1]) || (c2 != 0 && oz[c2 + 1]);
-        if (out) raw = Store<S>::load_raw(src + (Q - 1 - i) * k.stride + own);
+      R raw = Store<S>::load(ps.r[c2 + 1], no.o[c0 + 1][c1 + 1], i * sb);
+      if (WALL && i != Q / 2 && near) {
+        const R bb = Store<S>::load(ps.r[1], no.own, (Q - 1 - i) * sb);
+        const bool out = (c0 != 0 && no.ox[c0 + 1]) || (c1 != 0 && no.oy[c1 + 1]) || (c2 != 0 && ps.oz[c2 + 1]);
+        raw = out ? bb : raw;
       }
-      if (KEEP) h.v[i] = raw;
-      v[i] = Store<S>::to_float(raw);
+      h.v[i] = raw;
     }
+  }
+
+  // Deviation moments drho = sum h, dj_a = lambda_a sum c_ia h of fetched values.
+  __device__ static __forceinline__ void moments(const TileConst& k, const Pops<S, Q>& h, float& drho,
+                                                 float (&dj)[3]) {
+    float v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = h.get(i);
     float r, m[3];
     line_moments(v, r, m);
     // values are in storage scale: the factors carry 1/scale
@@ -242,8 +292,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   k.n0 = Ld->n[0];
   k.n1 = Ld->n[1];
   k.n2 = Ld->n[2];
-  k.plane = k.n0 * k.n1;
-  k.stride = Ld->stride;
+  k.slab_bytes = uint64_t(Q) * uint64_t(Ld->pstride) * sizeof(T);
   k.w0 = WALL && Ld->wall[0];
   k.w1 = WALL && Ld->wall[1];
   k.w2 = WALL && Ld->wall[2];
@@ -269,8 +318,8 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   k.scale = Ld->scale;
   k.om1 = Ld->om1;
   k.oms = Ld->oms;
-  const T* __restrict__ src = static_cast<const T*>(Ld->buf[parity]);
-  T* __restrict__ dst = static_cast<T*>(Ld->buf[parity ^ 1]);
+  const char* src = static_cast<const char*>(Ld->buf[parity]);
+  const char* dst = static_cast<const char*>(Ld->buf[parity ^ 1]);
 
   const int tiles0 = Ld->tiles[0], tiles1 = Ld->tiles[1], chunk = Ld->chunk;
   const int t0 = int(tl % tiles0);
@@ -349,64 +398,132 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   // the halo node's axis is a run-time value: select its constants once
   const float h_uref = hax == 0 ? k.uref[0] : k.uref[1];
   const float h_anom = hax == 0 ? k.anom[0] : k.anom[1];
-  auto halo = [&](int z, int b) {
-    if (has_halo) {
-      float dr, dj[3];
-      Pops<S, Q> unused;
-      P::template pull<false>(k, src, hx, hy, z, unused, dr, dj);
-      const float ir = recip(1.f + dr);
-      const float j = h_uref + (hax == 0 ? dj[0] : dj[1]);
-      const float u = j * ir;
-      hbase[b * hstep + hslot] = j * h_anom - j * u * u;
+  NodeOffs hno;
+  P::offsets(k, hx, hy, hno);
+  // anomaly of the halo node from its fetched populations, into LDS buffer b
+  auto halo_store = [&](const Pops<S, Q>& hv, int b) {
+    float dr, dj[3];
+    P::moments(k, hv, dr, dj);
+    const float ir = recip(1.f + dr);
+    const float j = h_uref + (hax == 0 ? dj[0] : dj[1]);
+    const float u = j * ir;
+    hbase[b * hstep + hslot] = j * h_anom - j * u * u;
+  };
+  // Plane index along the marched axis, reduced into the lattice: beyond it
+  // the index wraps (periodic axis) or, behind a wall, the plane is a ghost
+  // and the returned index is only a valid stand-in.
+  auto plane = [&](int zz, bool& ghost) {
+    ghost = false;
+    if (zz < 0) {
+      if (k.w2) ghost = true;
+      zz += k.n2;
     }
+    while (zz >= k.n2) {
+      if (k.w2) ghost = true;
+      zz -= k.n2;
+    }
+    return zz;
   };
 
-  const int cx = active ? gx : 0, cy = active ? gy : 0;
+  auto src_planes = [&](int zz) {
+    PlaneSrc ps;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int az = zz - (c - 1);
+      ps.oz[c] = WALL && k.w2 && (az < 0 || az >= k.n2);
+      ps.r[c] = rsrc(src + uint64_t(wrap(az, k.n2)) * k.slab_bytes);
+    }
+    return ps;
+  };
+  // The tile or its halo touches a wall of a tiled axis (conservative).
+  const bool near_xy = WALL && ((k.w0 && (x0 <= 1 || x0 + TXW >= k.n0 - 1)) ||
+                                (k.w1 && (y0 <= 1 || y0 + TYR >= k.n1 - 1)));
+  auto near = [&](const PlaneSrc& ps) { return near_xy || ps.oz[0] || ps.oz[2]; };
 
-  // ---- prologue: plane before the chunk (ring) and the first plane ----
-  Pops<S, Q> h, hn;
+  const int cx = active ? gx : 0, cy = active ? gy : 0;
+  NodeOffs no;
+  P::offsets(k, cx, cy, no);
+  const uint32_t sb0 = uint32_t(Ld->pstride) * uint32_t(sizeof(T));
+
+  // Populations in flight: while plane z is relaxed one set holds plane z,
+  // one plane z + 1 (fetched a plane ahead) and one receives plane z + 2; hp
+  // holds the halo node's next plane.
+  Pops<S, Q> P0, P1, P2, hp;
   float drho = 0.f, dj[3] = {0.f, 0.f, 0.f};
   float qc[3] = {0.f, 0.f, 0.f};  // anomaly of the current plane at this node
   float qprev = 0.f;
-  bool ghost_prev = false;
+  // ---- prologue: plane before the chunk (ring), the first plane, and the
+  // fetches of the second ----
   {
-    int zp = z0 - 1;
-    if (z0 == 0) { if (k.w2) ghost_prev = true; else zp = k.n2 - 1; }
-    if (active && !ghost_prev) {
+    bool ghost_prev;
+    const int zp = plane(z0 - 1, ghost_prev);
+    {
       float dr, djp[3];
-      P::template pull<false>(k, src, cx, cy, zp, hn, dr, djp);
+      const PlaneSrc sp = src_planes(zp);
+      P::fetch(sb0, sp, no, near(sp), P2);
+      P::moments(k, P2, dr, djp);
       qprev = anomaly(k, 2, djp[2], recip(1.f + dr));
     }
-    if (active) {
-      P::template pull<true>(k, src, cx, cy, z0, h, drho, dj);
+    const PlaneSrc s0 = src_planes(z0);
+    P::fetch(sb0, s0, no, near(s0), P0);
+    P::moments(k, P0, drho, dj);
+    {
       const float ir = recip(1.f + drho);
       qc[0] = anomaly(k, 0, dj[0], ir);
       if (D == 3) qc[1] = anomaly(k, 1, dj[1], ir);
       qc[2] = anomaly(k, 2, dj[2], ir);
       if (ghost_prev) qprev = -qc[2];
-      qxb[0][sx_own] = qc[0];
-      if (D == 3) qyb[0][sy_own] = qc[1];
+      if (active) {
+        qxb[0][sx_own] = qc[0];
+        if (D == 3) qyb[0][sy_own] = qc[1];
+      }
     }
-    halo(z0, 0);
+    bool ghost1;
+    const PlaneSrc s1 = src_planes(plane(z0 + 1, ghost1));
+    P::fetch(sb0, s1, no, near(s1), P1);
+    if (has_halo) {
+      P::fetch(sb0, s0, hno, near(s0), hp);
+      halo_store(hp, 0);
+      P::fetch(sb0, s1, hno, near(s1), hp);
+    }
   }
   __syncthreads();
 
-  for (int z = z0; z < z1; ++z) {
+  // One plane of the march. The three population sets rotate roles from
+  // plane to plane (the loop below is unrolled by three), so that no register
+  // receiving a fetch is ever copied before its load has landed.
+  auto march = [&](int z, const Pops<S, Q>& h, const Pops<S, Q>& pf1, Pops<S, Q>& pf2) {
     const int b = (z - z0) & 1;
-    // next plane (always pulled: its anomaly closes the ring)
-    int zn = z + 1;
-    bool ghost_next = false;
-    if (zn >= k.n2) { if (k.w2) ghost_next = true; else zn = 0; }
-    float drn = 0.f, djn[3] = {0.f, 0.f, 0.f}, qn[3] = {0.f, 0.f, 0.f};
+    // The array distance is made opaque per plane so that the per-direction
+    // offsets are formed in scalar registers where they are used rather than
+    // held across the march.
+    uint32_t sb = sb0;
+    asm("" : "+s"(sb) : "s"(z));
     const bool more = z + 1 < z1;
-    if (active && !ghost_next) {
-      P::template pull<true>(k, src, cx, cy, zn, hn, drn, djn);
+    bool ghost_next, ghost2;
+    plane(z + 1, ghost_next);
+    const PlaneSrc s2 = src_planes(plane(z + 2, ghost2));
+    // The fetches and the moments below are issued on every plane and by every
+    // lane (lanes beyond a ragged edge work on a clamped node; at the end of a
+    // chunk or behind a wall the fetched plane goes unused), so that the code
+    // between a fetch and its use is straight-line and the waits for the loads
+    // count exactly the memory operations issued after them. The node's own
+    // fetch precedes the halo's, whose branch then reuses its offsets.
+    // next plane (always needed: its anomaly closes the ring)
+    float drn, djn[3], qn[3] = {0.f, 0.f, 0.f};
+    {
+      P::moments(k, pf1, drn, djn);
       const float ir = recip(1.f + drn);
       qn[0] = anomaly(k, 0, djn[0], ir);
       if (D == 3) qn[1] = anomaly(k, 1, djn[1], ir);
       qn[2] = anomaly(k, 2, djn[2], ir);
     }
-    if (more) halo(z + 1, b ^ 1);
+    P::fetch(sb, s2, no, near(s2), pf2);
+    // halo of plane z + 1 (fetched one plane ahead), then the fetch of z + 2
+    if (has_halo) {
+      halo_store(hp, b ^ 1);
+      P::fetch(sb, s2, hno, near(s2), hp);
+    }
     const float qnext = ghost_next ? -qc[2] : qn[2];
 
     if (active) {
@@ -467,33 +584,50 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
         }
       }
 
-      const int own = cx + k.n0 * (cy + k.n1 * z);
+      const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
+      // Relaxation (Sec. 2.1, eq. LBGK) in storage scale,
+      //   o_i = (1 - w) h_i + w scale (f*_i - w_i) (+ scale F_i),
+      // with f*_i - w_i = drho B_i + dB_i from the product deviation. The
+      // factor w scale and the (c_x, c_y) partial products are applied once per
+      // node: w scale (drho X + dX) p_z + W_x W_y (w scale d_z) for D3Q27,
+      // w scale (drho W~_x + d_x) p_y + W_x (w scale d_y) for D2Q9.
+      const float drs = k.oms * drho;
+      float ds[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ds[a][c] = k.oms * d[a][c];
+      float A[3][3];  // [c_x][c_y]; D2Q9 uses [c_x][1]
+#pragma unroll
+      for (int c0 = 0; c0 < 3; ++c0)
+#pragma unroll
+        for (int c1 = 0; c1 < 3; ++c1) {
+          if (D == 3) {
+            const float X = p[0][c0] * p[1][c1];
+            const float dXs = ds[0][c0] * p[1][c1] + k.W[0][c0] * ds[1][c1];
+            A[c0][c1] = drs * X + dXs;
+          } else if (c1 == 1) {
+            A[c0][c1] = drs * p[0][c0] + ds[0][c0];
+          }
+        }
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         const int c0 = cq<D>(i, 0) + 1, c1 = cq<D>(i, 1) + 1, c2 = cq<D>(i, 2) + 1;
-        float hs, fr = 0.f;
-        if (D == 3) {
-          const float X = p[0][c0] * p[1][c1];
-          const float dX = d[0][c0] * p[1][c1] + k.W[0][c0] * d[1][c1];
-          const float B = X * p[2][c2];
-          const float dB = dX * p[2][c2] + k.WW[c0][c1] * d[2][c2];
-          hs = drho * B + dB;
-          if (FORCE) {
+        const float Wc = D == 3 ? k.WW[c0][c1] : k.W[0][c0];
+        float o = A[c0][c1] * p[2][c2] + Wc * ds[2][c2];
+        if (FORCE) {
+          float fr;
+          if (D == 3) {
             const float Y = pe[0][c0] * pe[1][c1];
             const float dY = e[0][c0] * (pe[1][c1] + e[1][c1]) + pe[0][c0] * e[1][c1];
             fr = rho * (dY * (pe[2][c2] + e[2][c2]) + Y * e[2][c2]);
+          } else {
+            fr = rho * (e[0][c0] * (pe[2][c2] + e[2][c2]) + pe[0][c0] * e[2][c2]);
           }
-        } else {
-          const float X = p[0][c0] * p[2][c2];
-          const float dX = d[0][c0] * p[2][c2] + k.W[0][c0] * d[2][c2];
-          hs = drho * X + dX;
-          if (FORCE) fr = rho * (e[0][c0] * (pe[2][c2] + e[2][c2]) + pe[0][c0] * e[2][c2]);
+          o += k.scale * fr;
         }
-        // relaxation (Sec. 2.1, eq. LBGK) in storage scale:
-        // o = (1 - w) h + w scale f* (+ scale F)
-        float o = k.om1 * h.get(i) + k.oms * hs;
-        if (FORCE) o += k.scale * fr;
-        Store<S>::store(dst + i * k.stride + own, o);
+        o = k.om1 * h.get(i) + o;
+        Store<S>::store(rd, no.own, i * sb, o);
       }
     }
 
@@ -502,7 +636,6 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       if (D == 3) qyb[b ^ 1][sy_own] = qn[1];
     }
     __syncthreads();
-    h = hn;
     drho = drn;
     dj[0] = djn[0];
     dj[1] = djn[1];
@@ -511,6 +644,11 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     qc[0] = qn[0];
     qc[1] = qn[1];
     qc[2] = qnext;
+  };
+  for (int z = z0; z < z1; z += 3) {
+    march(z, P0, P1, P2);
+    if (z + 1 < z1) march(z + 1, P1, P2, P0);
+    if (z + 2 < z1) march(z + 2, P2, P0, P1);
   }
 }
 

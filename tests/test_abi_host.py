@@ -56,6 +56,19 @@ def test_validation_rejects_bad_lattice_shapes():
     assert E.validate(p) == E.EINVAL  # more than 2^31 - 1 nodes
 
 
+@pytest.mark.parametrize("n,storage,ok", [((6400, 6400, 3), "f32", False), ((6400, 6400, 3), "f16", True),
+                                          ((1 << 27, 8), "f32", False), ((1 << 26, 8), "f16", True)])
+def test_validation_bounds_one_plane_slab(n, storage, ok):
+    # the Q direction arrays of one plane across the slowest axis must be
+    # addressable with 32-bit byte offsets
+    p = E.make_params(n, T=0.5, omega=1.0, storage=storage)
+    if ok:
+        assert E.validate(p) == E.OK
+    else:
+        assert E.validate(p) == E.EINVAL
+        assert "per plane" in E._lib.elbm_last_error().decode()
+
+
 @pytest.mark.parametrize("n,storage,es", [((64, 64), "f32", 4), ((256, 256, 256), "f32", 4),
                                           ((384, 192, 192), "f16", 2), ((100, 77), "bf16", 2)])
 def test_footprint_covers_two_population_buffers(n, storage, es):
