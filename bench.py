@@ -51,6 +51,8 @@ def parse_args():
                     help="only run a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the served mixed stream (0: skip the serving leg)")
+    ap.add_argument("--hit-only", action="store_true",
+                    help="only the 256^3 turbulence legs (no D2Q9 or serving leg): for per-kernel profiles")
     return ap.parse_args()
 
 
@@ -312,9 +314,9 @@ def main():
                             "enstrophy_last": r["enstrophy_last"], "min_rho": r["final_min_rho"]}
                         for s, r in runs.items()},
     }
-    if args.n == N_HIT:
+    if args.n == N_HIT and not args.hit_only:
         out["d2q9"] = d2q9_leg()
-    if args.serve_requests > 0 and args.n == N_HIT:
+    if args.serve_requests > 0 and args.n == N_HIT and not args.hit_only:
         out["serving"] = serving_leg(args.serve_requests)
         print(f"# serving: {out['serving']['solves_per_s']:.1f} solves/s, p50 {out['serving']['p50_latency_s']:.3f} s, "
               f"p99 {out['serving']['p99_latency_s']:.3f} s", file=sys.stderr, flush=True)

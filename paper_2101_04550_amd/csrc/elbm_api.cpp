@@ -37,7 +37,7 @@ struct elbm_lattice {
   hipEvent_t event = nullptr;
   int64_t step = 0;
   int64_t ntiles = 0;
-  bool wall = false, force = false;
+  bool wall = false, force = false, staged = false;
   LatticeDesc desc{};
   LatticeConst64 c64{};
 };
@@ -53,7 +53,7 @@ struct elbm_batch_s {
   // one table per kernel class: header followed by `capacity` descriptors
   std::map<int, char*> dev_tables;
   char* host_stage = nullptr;  // pinned, kClasses tables
-  std::map<std::tuple<uint32_t, int64_t, std::vector<int>>, hipGraphExec_t> graphs;
+  std::map<std::tuple<uint64_t, int64_t, std::vector<int>>, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -76,13 +76,22 @@ int32_t hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, #call);    \
   } while (0)
 
-constexpr int kClasses = 24;  // D (2) x storage (3) x wall (2) x force (2)
+constexpr int kClasses = 48;  // D (2) x storage (3) x wall (2) x force (2) x staged (2)
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-int class_of(int D, int storage, bool wall, bool force) {
-  return (((D == 3) * 3 + storage) * 2 + (wall ? 1 : 0)) * 2 + (force ? 1 : 0);
+int class_of(int D, int storage, bool wall, bool force, bool staged) {
+  return ((((D == 3) * 3 + storage) * 2 + (wall ? 1 : 0)) * 2 + (force ? 1 : 0)) * 2 + (staged ? 1 : 0);
+}
+
+// Whether a lattice takes the LDS-staged step kernel: periodic D3Q27 with
+// 16-bit storage and full tiles (n_x % 64 == 0, n_y % kRowsStaged == 0).
+// ELBM_STAGED=0 forces the register-pull kernel (for measurements).
+bool use_staged(const elbm_params& p, bool wall) {
+  if (const char* s = std::getenv("ELBM_STAGED"))
+    if (s[0] == '0') return false;
+  return p.lattice == 27 && p.storage != ELBM_STORE_F32 && !wall && p.n[0] % 64 == 0 && p.n[1] % kRowsStaged == 0;
 }
 
 bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
@@ -260,13 +269,13 @@ void fill_desc(elbm_lattice* h) {
   d.buf[1] = h->buf[1];
   d.pstride = h->pstride;
   const int txw = D == 3 ? kTileX3 : 64 * kStrips2;
-  const int tyr = D == 3 ? kRows3 : 1;
+  const int tyr = D == 3 ? (h->staged ? kRowsStaged : kRows3) : 1;
   d.tiles[0] = (d.n[0] + txw - 1) / txw;
   d.tiles[1] = (d.n[1] + tyr - 1) / tyr;
   int cus = 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
     cus = 256;
-  const int bpc = step_blocks_per_cu(D, p.storage, h->wall, h->force);
+  const int bpc = step_blocks_per_cu(D, p.storage, h->wall, h->force, h->staged);
   d.chunk = choose_chunk(D, int64_t(d.tiles[0]) * d.tiles[1], d.n[2], int64_t(cus) * bpc);
   d.tiles[2] = (d.n[2] + d.chunk - 1) / d.chunk;
   d.ntiles = int64_t(d.tiles[0]) * d.tiles[1] * d.tiles[2];
@@ -428,6 +437,7 @@ int32_t elbm_create(const elbm_params* p, void* dev_buf, size_t bytes, void* hip
   h->wall = false;
   for (int a = 0; a < h->D; ++a) h->wall = h->wall || p->bc[a] == ELBM_BC_BOUNCEBACK;
   h->force = p->force[0] != 0.0 || p->force[1] != 0.0 || (h->D == 3 && p->force[2] != 0.0);
+  h->staged = use_staged(*p, h->wall);
   hipError_t e = hipGetDevice(&h->device);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&h->event, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -486,7 +496,8 @@ int32_t elbm_step(elbm_handle h, int64_t nsteps) {
   if (s) return s;
   const int grid = grid_for_tiles(h->ntiles);
   for (int64_t k = 0; k < nsteps; ++k) {
-    HIPCHK(launch_step(h->D, h->p.storage, h->wall, h->force, h->hdr_dev, h->desc_dev, h->step, grid, h->stream));
+    HIPCHK(launch_step(h->D, h->p.storage, h->wall, h->force, h->staged, h->hdr_dev, h->desc_dev, h->step, grid,
+                       h->stream));
     ++h->step;
     if (h->p.diag_every > 0 && h->step % h->p.diag_every == 0) {
       s = run_diag(h, true);
@@ -698,13 +709,13 @@ int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps
   for (int32_t k = 0; k < count; ++k) {
     if (steps[k] == 0) continue;
     const elbm_lattice* h = hs[k];
-    members[class_of(h->D, h->p.storage, h->wall, h->force)].push_back(k);
+    members[class_of(h->D, h->p.storage, h->wall, h->force, h->staged)].push_back(k);
   }
-  uint32_t mask = 0;
+  uint64_t mask = 0;
   std::vector<int> grids;
   for (int c = 0; c < kClasses; ++c) {
     if (members[c].empty()) continue;
-    mask |= 1u << c;
+    mask |= uint64_t(1) << c;
     char* hostt = b->host_stage + size_t(c) * tbytes;
     auto* hdr = reinterpret_cast<TableHeader*>(hostt);
     auto* tab = reinterpret_cast<LatticeDesc*>(hostt + hbytes);
@@ -740,7 +751,7 @@ int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps
     HIPCHK(hipStreamWaitEvent(b->stream, hs[k]->event, 0));
   }
   for (int c = 0; c < kClasses; ++c) {
-    if (!(mask & (1u << c))) continue;
+    if (!(mask & (uint64_t(1) << c))) continue;
     const size_t n = hbytes + size_t(members[c].size()) * sizeof(LatticeDesc);
     HIPCHK(hipMemcpyAsync(b->dev_tables[c], b->host_stage + size_t(c) * tbytes, n, hipMemcpyHostToDevice, b->stream));
   }
@@ -751,14 +762,15 @@ int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps
     for (int64_t sub = 0; sub < smax; ++sub) {
       int gi = 0;
       for (int c = 0; c < kClasses; ++c) {
-        if (!(mask & (1u << c))) continue;
-        const int D = c >= 12 ? 3 : 2;
-        const int storage = (c / 4) % 3;
-        const bool wall = (c / 2) % 2;
-        const bool force = c % 2;
+        if (!(mask & (uint64_t(1) << c))) continue;
+        const int D = c >= kClasses / 2 ? 3 : 2;
+        const int storage = (c / 8) % 3;
+        const bool wall = (c / 4) % 2;
+        const bool force = (c / 2) % 2;
+        const bool staged = c % 2;
         const auto* hdr = reinterpret_cast<const TableHeader*>(b->dev_tables[c]);
         const auto* tab = reinterpret_cast<const LatticeDesc*>(b->dev_tables[c] + hbytes);
-        HIPCHK(launch_step(D, storage, wall, force, hdr, tab, sub, grids[gi++], st));
+        HIPCHK(launch_step(D, storage, wall, force, staged, hdr, tab, sub, grids[gi++], st));
       }
     }
     return ELBM_OK;

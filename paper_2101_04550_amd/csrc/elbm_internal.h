@@ -30,8 +30,16 @@ namespace elbm {
 #ifndef ELBM_TY3
 #define ELBM_TY3 8
 #endif
+#ifndef ELBM_TYS
+#define ELBM_TYS 16
+#endif
+#ifndef ELBM_NSTAGE
+#define ELBM_NSTAGE 2
+#endif
 constexpr int kTileX3 = ELBM_TX3;  // x width of a D3Q27 tile
 constexpr int kRows3 = ELBM_TY3;   // y rows of a D3Q27 tile
+constexpr int kRowsStaged = ELBM_TYS;     // y rows of a tile of the LDS-staged kernel (x width 64)
+constexpr int kStagesStaged = ELBM_NSTAGE;  // planes the LDS-staged kernel holds in LDS (2 or 3)
 constexpr int kStrips2 = 4;        // 64-wide strips of a D2Q9 tile -> 256 threads
 constexpr int kDiagBlocks = 1024;  // fixed grid of the diagnostic reductions
 constexpr int kRec = 16;           // doubles per diagnostic record / partial
@@ -105,11 +113,12 @@ struct LatticeConst64 {
 };
 
 // ---- launchers (defined in the .hip translation units) ----
-hipError_t launch_step(int D, int storage, bool wall, bool force, const TableHeader* hdr,
+// staged: the LDS-staged D3Q27 kernel for 16-bit storage (periodic, full tiles).
+hipError_t launch_step(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
                        const LatticeDesc* table, int64_t substep, int grid, hipStream_t st);
 int step_block_threads(int D);
 // Resident step blocks per compute unit for a kernel class (occupancy query).
-int step_blocks_per_cu(int D, int storage, bool wall, bool force);
+int step_blocks_per_cu(int D, int storage, bool wall, bool force, bool staged);
 
 hipError_t launch_init(const LatticeConst64& c, const double* stage, int64_t cell0, int64_t count,
                        void* dst, hipStream_t st);

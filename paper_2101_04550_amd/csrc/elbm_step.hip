@@ -45,6 +45,7 @@
 
 #include "elbm_internal.h"
 
+
 namespace elbm {
 namespace {
 
@@ -101,6 +102,12 @@ struct Store<2> {
     __builtin_amdgcn_raw_buffer_store_b16(__bfloat16_as_ushort(__float2bfloat16(v)), r, off, soff, kNonTemporal);
   }
 };
+
+// Waits until this wave's vector-memory operations (loads and stores) are
+// complete: vmcnt(0), expcnt and lgkmcnt left open (gfx9 encoding).
+__device__ __forceinline__ void drain_vm() { __builtin_amdgcn_s_waitcnt(0xF70); }
+// ... and its LDS / scalar-memory operations as well.
+__device__ __forceinline__ void drain_all() { __builtin_amdgcn_s_waitcnt(0); }
 
 // 1/x with the hardware reciprocal (1 ulp).
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -280,19 +287,14 @@ __device__ __forceinline__ float anomaly(const TileConst& k, int a, float dja, f
   return j * k.anom[a] - j * u * u;
 }
 
-template <int D, int S, bool WALL, bool FORCE>
-__device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, int64_t tl, int parity,
-                                          float* __restrict__ sq) {
-  using G = Geo<D, S>;
-  using T = typename Store<S>::T;
-  using P = Puller<D, S, WALL>;
-  constexpr int Q = G::Q, TXW = G::TXW, TYR = G::TYR;
-
-  TileConst k;
+// Copies a lattice's per-tile constants out of its descriptor; qbytes = Q
+// times the element size.
+template <bool WALL>
+__device__ __forceinline__ void load_const(const LatticeDesc* __restrict__ Ld, uint32_t qbytes, TileConst& k) {
   k.n0 = Ld->n[0];
   k.n1 = Ld->n[1];
   k.n2 = Ld->n[2];
-  k.slab_bytes = uint64_t(Q) * uint64_t(Ld->pstride) * sizeof(T);
+  k.slab_bytes = uint64_t(Ld->pstride) * qbytes;
   k.w0 = WALL && Ld->wall[0];
   k.w1 = WALL && Ld->wall[1];
   k.w2 = WALL && Ld->wall[2];
@@ -318,6 +320,114 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   k.scale = Ld->scale;
   k.om1 = Ld->om1;
   k.oms = Ld->oms;
+}
+
+// Collision of one node (Sec. 2.1, eq. LBGK; Sec. 2.2-2.4): from the
+// deviation moments (drho, dj), the central differences of the anomaly Gd
+// (already divided by 2 lambda_a) and the pulled values hval(i) (storage
+// scale), emits the relaxed and forced populations o_i in storage scale
+// through emit(i, o_i).
+template <int D, bool FORCE, class HV, class EMIT>
+__device__ __forceinline__ void collide(const TileConst& k, float drho, const float (&dj)[3], const float (&Gd)[3],
+                                        HV hval, EMIT emit) {
+  constexpr int Q = D == 3 ? 27 : 9;
+  const float rho = 1.f + drho;
+  const float ir = recip(rho);
+  float du[3], dP[3], d[3][3], p[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (D == 2 && a == 1) {
+      du[a] = 0.f;
+      dP[a] = 0.f;
+    } else {
+      du[a] = (dj[a] - drho * k.uref[a]) * ir;
+      const float u = k.uref[a] + du[a];
+      dP[a] = du[a] * (u + k.uref[a]) + k.coef * Gd[a] * ir;
+    }
+    const float t1v = du[a] * k.inv_lam[a];
+    const float t2v = dP[a] * k.inv_lam2[a];
+    d[a][0] = 0.5f * (t2v - t1v);
+    d[a][1] = -t2v;
+    d[a][2] = 0.5f * (t2v + t1v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[a][c] = k.W[a][c] + d[a][c];
+  }
+
+  // body force: increments of the equilibrium triplets from u to u + g
+  float pe[3][3], e[3][3];
+  if (FORCE) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float u = k.uref[a] + du[a];
+      const float t1v = du[a] * k.inv_lam[a];
+      const float t2v = du[a] * (u + k.uref[a]) * k.inv_lam2[a];
+      pe[a][0] = k.W[a][0] + 0.5f * (t2v - t1v);
+      pe[a][1] = k.W[a][1] - t2v;
+      pe[a][2] = k.W[a][2] + 0.5f * (t2v + t1v);
+      const float gg = k.g[a] * (2.f * u + k.g[a]);
+      const float s1 = k.g[a] * k.inv_lam[a];
+      const float s2 = gg * k.inv_lam2[a];
+      e[a][0] = 0.5f * (s2 - s1);
+      e[a][1] = -s2;
+      e[a][2] = 0.5f * (s2 + s1);
+    }
+  }
+
+  // Relaxation (Sec. 2.1, eq. LBGK) in storage scale,
+  //   o_i = (1 - w) h_i + w scale (f*_i - w_i) (+ scale F_i),
+  // with f*_i - w_i = drho B_i + dB_i from the product deviation. The
+  // factor w scale and the (c_x, c_y) partial products are applied once per
+  // node: w scale (drho X + dX) p_z + W_x W_y (w scale d_z) for D3Q27,
+  // w scale (drho W~_x + d_x) p_y + W_x (w scale d_y) for D2Q9.
+  const float drs = k.oms * drho;
+  float ds[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ds[a][c] = k.oms * d[a][c];
+  float A[3][3];  // [c_x][c_y]; D2Q9 uses [c_x][1]
+#pragma unroll
+  for (int c0 = 0; c0 < 3; ++c0)
+#pragma unroll
+    for (int c1 = 0; c1 < 3; ++c1) {
+      if (D == 3) {
+        const float X = p[0][c0] * p[1][c1];
+        const float dXs = ds[0][c0] * p[1][c1] + k.W[0][c0] * ds[1][c1];
+        A[c0][c1] = drs * X + dXs;
+      } else if (c1 == 1) {
+        A[c0][c1] = drs * p[0][c0] + ds[0][c0];
+      }
+    }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int c0 = cq<D>(i, 0) + 1, c1 = cq<D>(i, 1) + 1, c2 = cq<D>(i, 2) + 1;
+    const float Wc = D == 3 ? k.WW[c0][c1] : k.W[0][c0];
+    float o = A[c0][c1] * p[2][c2] + Wc * ds[2][c2];
+    if (FORCE) {
+      float fr;
+      if (D == 3) {
+        const float Y = pe[0][c0] * pe[1][c1];
+        const float dY = e[0][c0] * (pe[1][c1] + e[1][c1]) + pe[0][c0] * e[1][c1];
+        fr = rho * (dY * (pe[2][c2] + e[2][c2]) + Y * e[2][c2]);
+      } else {
+        fr = rho * (e[0][c0] * (pe[2][c2] + e[2][c2]) + pe[0][c0] * e[2][c2]);
+      }
+      o += k.scale * fr;
+    }
+    emit(i, k.om1 * hval(i) + o);
+  }
+}
+
+template <int D, int S, bool WALL, bool FORCE>
+__device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, int64_t tl, int parity,
+                                          float* __restrict__ sq) {
+  using G = Geo<D, S>;
+  using T = typename Store<S>::T;
+  using P = Puller<D, S, WALL>;
+  constexpr int Q = G::Q, TXW = G::TXW, TYR = G::TYR;
+
+  TileConst k;
+  load_const<WALL>(Ld, Q * sizeof(T), k);
   const char* src = static_cast<const char*>(Ld->buf[parity]);
   const char* dst = static_cast<const char*>(Ld->buf[parity ^ 1]);
 
@@ -337,8 +447,11 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   const int gx = x0 + lx, gy = y0 + ly;
   const bool active = gx < k.n0 && gy < k.n1;
 
-  float* qxb[2] = {sq, sq + G::LX};
-  float* qyb[2] = {sq + 2 * G::LX, sq + 2 * G::LX + G::LY};
+  // anomaly exchange in LDS, double buffered by plane: axis 0 at
+  // sq[b LX + slot], axis 1 at sq[2 LX + b LY + slot] (plain indices into the
+  // shared array keep every access an LDS instruction)
+  auto QX = [&](int b, int slot) -> float& { return sq[b * G::LX + slot]; };
+  auto QY = [&](int b, int slot) -> float& { return sq[2 * G::LX + b * G::LY + slot]; };
 
   // ---- neighbour slots of the tiled axes (fixed over the march) ----
   const int rowx = ly * (TXW + 2);
@@ -392,8 +505,8 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       if (hx >= k.n0) { if (k.w0) has_halo = false; else hx = 0; }
     }
   }
-  float* hbase = hax == 0 ? sq : sq + 2 * G::LX;  // buffer 0 of the halo's axis
-  const int hstep = hax == 0 ? G::LX : G::LY;     // offset to buffer 1
+  const int hofs = hax == 0 ? 0 : 2 * G::LX;     // buffer 0 of the halo's axis
+  const int hstep = hax == 0 ? G::LX : G::LY;    // offset to buffer 1
 
   // the halo node's axis is a run-time value: select its constants once
   const float h_uref = hax == 0 ? k.uref[0] : k.uref[1];
@@ -407,7 +520,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     const float ir = recip(1.f + dr);
     const float j = h_uref + (hax == 0 ? dj[0] : dj[1]);
     const float u = j * ir;
-    hbase[b * hstep + hslot] = j * h_anom - j * u * u;
+    sq[hofs + b * hstep + hslot] = j * h_anom - j * u * u;
   };
   // Plane index along the marched axis, reduced into the lattice: beyond it
   // the index wraps (periodic axis) or, behind a wall, the plane is a ghost
@@ -474,8 +587,8 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       qc[2] = anomaly(k, 2, dj[2], ir);
       if (ghost_prev) qprev = -qc[2];
       if (active) {
-        qxb[0][sx_own] = qc[0];
-        if (D == 3) qyb[0][sy_own] = qc[1];
+        QX(0, sx_own) = qc[0];
+        if (D == 3) QY(0, sy_own) = qc[1];
       }
     }
     bool ghost1;
@@ -519,6 +632,12 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       qn[2] = anomaly(k, 2, djn[2], ir);
     }
     P::fetch(sb, s2, no, near(s2), pf2);
+    // Memory drains (here, before the collision and after its stores): with
+    // the next planes' reads left in flight, the halo and ring rows that
+    // neighbouring tiles re-read drop out of L2 (about 18% more HBM reads
+    // than the algorithmic bytes at 256^3 FP32, against 6% with the drains,
+    // and 6% longer steps).
+    drain_vm();
     // halo of plane z + 1 (fetched one plane ahead), then the fetch of z + 2
     if (has_halo) {
       halo_store(hp, b ^ 1);
@@ -528,112 +647,28 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
 
     if (active) {
       // ---- collision of plane z ----
-      const float* qx = qxb[b];
-      const float qxm = gxm ? -qc[0] : qx[sxm];
-      const float qxp = gxp ? -qc[0] : qx[sxp];
+      drain_all();
+      const float qxm = gxm ? -qc[0] : QX(b, sxm);
+      const float qxp = gxp ? -qc[0] : QX(b, sxp);
       float Gd[3];
       Gd[0] = (qxp - qxm) * k.hil[0];
       Gd[1] = 0.f;
       if (D == 3) {
-        const float* qy = qyb[b];
-        const float qym = gym ? -qc[1] : qy[sym];
-        const float qyp = gyp ? -qc[1] : qy[syp];
+        const float qym = gym ? -qc[1] : QY(b, sym);
+        const float qyp = gyp ? -qc[1] : QY(b, syp);
         Gd[1] = (qyp - qym) * k.hil[1];
       }
       Gd[2] = (qnext - qprev) * k.hil[2];
 
-      const float rho = 1.f + drho;
-      const float ir = recip(rho);
-      float du[3], dP[3], d[3][3], p[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        if (D == 2 && a == 1) {
-          du[a] = 0.f;
-          dP[a] = 0.f;
-        } else {
-          du[a] = (dj[a] - drho * k.uref[a]) * ir;
-          const float u = k.uref[a] + du[a];
-          dP[a] = du[a] * (u + k.uref[a]) + k.coef * Gd[a] * ir;
-        }
-        const float t1v = du[a] * k.inv_lam[a];
-        const float t2v = dP[a] * k.inv_lam2[a];
-        d[a][0] = 0.5f * (t2v - t1v);
-        d[a][1] = -t2v;
-        d[a][2] = 0.5f * (t2v + t1v);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) p[a][c] = k.W[a][c] + d[a][c];
-      }
-
-      // body force: increments of the equilibrium triplets from u to u + g
-      float pe[3][3], e[3][3];
-      if (FORCE) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const float u = k.uref[a] + du[a];
-          const float t1v = du[a] * k.inv_lam[a];
-          const float t2v = du[a] * (u + k.uref[a]) * k.inv_lam2[a];
-          pe[a][0] = k.W[a][0] + 0.5f * (t2v - t1v);
-          pe[a][1] = k.W[a][1] - t2v;
-          pe[a][2] = k.W[a][2] + 0.5f * (t2v + t1v);
-          const float gg = k.g[a] * (2.f * u + k.g[a]);
-          const float s1 = k.g[a] * k.inv_lam[a];
-          const float s2 = gg * k.inv_lam2[a];
-          e[a][0] = 0.5f * (s2 - s1);
-          e[a][1] = -s2;
-          e[a][2] = 0.5f * (s2 + s1);
-        }
-      }
-
       const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
-      // Relaxation (Sec. 2.1, eq. LBGK) in storage scale,
-      //   o_i = (1 - w) h_i + w scale (f*_i - w_i) (+ scale F_i),
-      // with f*_i - w_i = drho B_i + dB_i from the product deviation. The
-      // factor w scale and the (c_x, c_y) partial products are applied once per
-      // node: w scale (drho X + dX) p_z + W_x W_y (w scale d_z) for D3Q27,
-      // w scale (drho W~_x + d_x) p_y + W_x (w scale d_y) for D2Q9.
-      const float drs = k.oms * drho;
-      float ds[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) ds[a][c] = k.oms * d[a][c];
-      float A[3][3];  // [c_x][c_y]; D2Q9 uses [c_x][1]
-#pragma unroll
-      for (int c0 = 0; c0 < 3; ++c0)
-#pragma unroll
-        for (int c1 = 0; c1 < 3; ++c1) {
-          if (D == 3) {
-            const float X = p[0][c0] * p[1][c1];
-            const float dXs = ds[0][c0] * p[1][c1] + k.W[0][c0] * ds[1][c1];
-            A[c0][c1] = drs * X + dXs;
-          } else if (c1 == 1) {
-            A[c0][c1] = drs * p[0][c0] + ds[0][c0];
-          }
-        }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const int c0 = cq<D>(i, 0) + 1, c1 = cq<D>(i, 1) + 1, c2 = cq<D>(i, 2) + 1;
-        const float Wc = D == 3 ? k.WW[c0][c1] : k.W[0][c0];
-        float o = A[c0][c1] * p[2][c2] + Wc * ds[2][c2];
-        if (FORCE) {
-          float fr;
-          if (D == 3) {
-            const float Y = pe[0][c0] * pe[1][c1];
-            const float dY = e[0][c0] * (pe[1][c1] + e[1][c1]) + pe[0][c0] * e[1][c1];
-            fr = rho * (dY * (pe[2][c2] + e[2][c2]) + Y * e[2][c2]);
-          } else {
-            fr = rho * (e[0][c0] * (pe[2][c2] + e[2][c2]) + pe[0][c0] * e[2][c2]);
-          }
-          o += k.scale * fr;
-        }
-        o = k.om1 * h.get(i) + o;
-        Store<S>::store(rd, no.own, i * sb, o);
-      }
+      collide<D, FORCE>(k, drho, dj, Gd, [&](int i) { return h.get(i); },
+                        [&](int i, float o) { Store<S>::store(rd, no.own, i * sb, o); });
     }
+    drain_vm();
 
     if (more && active) {
-      qxb[b ^ 1][sx_own] = qn[0];
-      if (D == 3) qyb[b ^ 1][sy_own] = qn[1];
+      QX(b ^ 1, sx_own) = qn[0];
+      if (D == 3) QY(b ^ 1, sy_own) = qn[1];
     }
     __syncthreads();
     drho = drn;
@@ -649,6 +684,310 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     march(z, P0, P1, P2);
     if (z + 1 < z1) march(z + 1, P1, P2, P0);
     if (z + 2 < z1) march(z + 2, P2, P0, P1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged D3Q27 step for 16-bit storage.
+//
+// The kernel above issues one narrow load per pulled value; with 2-byte
+// elements that instruction stream, rather than HBM, sets its pace. Here a
+// block stages, for every direction i, the rows of plane z - c_iz that its
+// tile and halo nodes pull direction i from, in LDS: each row's 64 interior
+// nodes with 16-byte loads and the node pairs left and right of the tile with
+// 4-byte loads, three planes deep, so that the loads of plane z + 2 are in
+// flight while plane z is relaxed. A pull is then an LDS read at an offset
+// fixed per direction. It applies to periodic D3Q27 lattices whose n_x is a
+// multiple of 64 and n_y a multiple of 8 (full tiles); the others take the
+// kernel above.
+//
+// Staged row layout (bytes): [0, 128) the 64 interior nodes x0 ... x0 + 63,
+// [128, 132) the pair x0 - 2, x0 - 1, [132, 136) the pair x0 + 64, x0 + 65,
+// padding to 144. Direction i's box holds rows y0 - 1 - c_iy ... y0 + 8 - c_iy,
+// so a node of tile row ly reads row ly + 1 of every box.
+// ---------------------------------------------------------------------------
+namespace lds {
+constexpr int TX = 64, TY = kRowsStaged, NT = TX * TY;
+constexpr int ROWB = 144;
+constexpr int BOX = (TY + 2) * ROWB;
+constexpr int STAGE = 27 * BOX;
+constexpr int NSTAGE = kStagesStaged;
+constexpr int LXF = TY * (TX + 2);  // anomaly exchange, axis 0 (floats per buffer)
+constexpr int LYF = (TY + 2) * TX;  // anomaly exchange, axis 1
+constexpr int BYTES = NSTAGE * STAGE + 2 * (LXF + LYF) * 4;
+constexpr int CHUNKS = 9 * (TY + 2) * 8;  // 16-byte interior loads per c_z group
+constexpr int PAIRS = 9 * (TY + 2) * 2;   // 4-byte side-pair loads per c_z group
+static_assert(CHUNKS <= 2 * NT && PAIRS <= NT, "staging covers a group in two passes");
+static_assert(STAGE % 16 == 0 && BOX % 16 == 0 && ROWB % 16 == 0, "16-byte LDS stores stay aligned");
+static_assert(NSTAGE == 2 || NSTAGE == 3, "two or three staged planes");
+static_assert(BYTES <= 160 * 1024, "LDS of one block");
+static_assert(NT <= 1024 && TY % 2 == 0, "one block per tile");
+}  // namespace lds
+
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+
+// Byte of staged column dx = x - x0 (dx in [-2, 65]) within a row.
+__device__ __forceinline__ int col_byte(int dx) {
+  return dx < 0 ? 128 + 2 * (dx + 2) : (dx < 64 ? 2 * dx : 132 + 2 * (dx - 64));
+}
+
+template <int S, bool FORCE>
+__device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld, int64_t tl, int parity,
+                                              unsigned char* __restrict__ smem) {
+  using namespace lds;
+  using T = typename Store<S>::T;
+  using R = typename Store<S>::R;
+  static_assert(sizeof(T) == 2, "16-bit storage only");
+  constexpr int Q = 27;
+
+  TileConst k;
+  load_const<false>(Ld, Q * sizeof(T), k);
+  const char* src = static_cast<const char*>(Ld->buf[parity]);
+  const char* dst = static_cast<const char*>(Ld->buf[parity ^ 1]);
+  const uint32_t sb0 = uint32_t(Ld->pstride) * 2u;
+
+  const int tiles0 = Ld->tiles[0], tiles1 = Ld->tiles[1], chunk = Ld->chunk;
+  const int t0 = int(tl % tiles0);
+  const int64_t rr = tl / tiles0;
+  const int t1 = int(rr % tiles1);
+  const int t2 = int(rr / tiles1);
+  const int x0 = t0 * TX, y0 = t1 * TY;
+  const int z0 = t2 * chunk;
+  const int z1 = min(z0 + chunk, k.n2);
+
+  const int tid = threadIdx.x;
+  const int lx = tid & 63, ly = tid >> 6;
+  const int gx = x0 + lx, gy = y0 + ly;
+
+  float* anom = reinterpret_cast<float*>(smem + NSTAGE * STAGE);
+  auto QX = [&](int b, int slot) -> float& { return anom[b * LXF + slot]; };
+  auto QY = [&](int b, int slot) -> float& { return anom[2 * LXF + b * LYF + slot]; };
+  // anomaly slots of the node and of its tiled-axis neighbours (periodic, full tiles)
+  const int sx_own = ly * (TX + 2) + lx + 1, sxm = sx_own - 1, sxp = sx_own + 1;
+  const int sy_own = (ly + 1) * TX + lx, sym = sy_own - TX, syp = sy_own + TX;
+
+  // halo node of this thread: tid < 128 the rows y0 - 1 and y0 + 8, then the
+  // columns x0 - 1 and x0 + 64 (tile-local coordinates hx, hy)
+  const bool has_halo = tid < 2 * TX + 2 * TY;
+  int hx = 0, hy = 0, hslot = 0, hax = 0;
+  if (tid < 2 * TX) {
+    const int side = tid >> 6;
+    hx = lx;
+    hy = side ? TY : -1;
+    hslot = (side ? (TY + 1) * TX : 0) + lx;
+    hax = 1;
+  } else if (has_halo) {
+    const int q = tid - 2 * TX, side = q / TY, row = q % TY;
+    hx = side ? TX : -1;
+    hy = row;
+    hslot = row * (TX + 2) + (side ? TX + 1 : 0);
+  }
+  const float h_uref = hax == 0 ? k.uref[0] : k.uref[1];
+  const float h_anom = hax == 0 ? k.anom[0] : k.anom[1];
+  const int hofs = hax == 0 ? 0 : 2 * LXF;  // the halo's axis: buffer 0, and the offset to buffer 1
+  const int hstep = hax == 0 ? LXF : LYF;
+
+  // LDS read bases (bytes within a stage) per c_x, of the node and of its halo node
+  int rb[3], hb[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    rb[c] = (ly + 1) * ROWB + col_byte(lx - (c - 1));
+    hb[c] = (hy + 1) * ROWB + col_byte(hx - (c - 1));
+  }
+  auto pull_lds = [&](const unsigned char* stg, const int (&base)[3], int i) -> R {
+    const int c0 = cq<3>(i, 0);
+    return *reinterpret_cast<const R*>(stg + i * BOX + base[c0 + 1]);
+  };
+  // deviation moments of the values a node pulls from stage stg
+  auto moments = [&](const unsigned char* stg, const int (&base)[3], float& drho, float (&dj)[3]) {
+    float v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = Store<S>::to_float(pull_lds(stg, base, i));
+    float r, m[3];
+    Puller<3, S, false>::line_moments(v, r, m);
+    drho = r * k.inv_scale;
+    dj[0] = k.mfac[0] * m[0];
+    dj[1] = k.mfac[1] * m[1];
+    dj[2] = k.mfac[2] * m[2];
+  };
+
+  // ---- staging: this thread's loads (fixed along the march) ----
+  // Interior chunks a and b (the second clamped into range: a duplicate load
+  // stores the same bytes twice) and one side pair, per c_z group; group g
+  // covers directions 9 g ... 9 g + 8, i.e. array j of the group is direction
+  // 9 g + j, so group g adds 9 g arrays to both offsets.
+  uint32_t voff[3];
+  int loff[3];
+  {
+    const int items[2] = {tid, min(tid + NT, CHUNKS - 1)};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int it = items[u];
+      const int j = it / ((TY + 2) * 8), r = (it >> 3) % (TY + 2), q = it & 7;
+      const int c1 = j / 3 - 1;
+      int ys = y0 - 1 - c1 + r;
+      ys = ys < 0 ? ys + k.n1 : (ys >= k.n1 ? ys - k.n1 : ys);
+      voff[u] = j * sb0 + uint32_t(ys * k.n0 + x0) * 2u + 16u * q;
+      loff[u] = j * BOX + r * ROWB + 16 * q;
+    }
+    const int pr = min(tid, PAIRS - 1);
+    const int j = pr / ((TY + 2) * 2), r = (pr >> 1) % (TY + 2), side = pr & 1;
+    const int c1 = j / 3 - 1;
+    int ys = y0 - 1 - c1 + r;
+    ys = ys < 0 ? ys + k.n1 : (ys >= k.n1 ? ys - k.n1 : ys);
+    const int xs = side ? (x0 + TX == k.n0 ? 0 : x0 + TX) : (x0 == 0 ? k.n0 - 2 : x0 - 2);
+    voff[2] = j * sb0 + uint32_t(ys * k.n0 + xs) * 2u;
+    loff[2] = j * BOX + r * ROWB + 128 + 4 * side;
+  }
+  struct Staged {
+    u32x4 a[3], b[3];
+    uint32_t pr[3];
+  };
+  // issues the loads of the stage of node plane p (direction i from plane p - c_iz)
+  auto stage_load = [&](int p, uint32_t sb, Staged& g) {
+#pragma unroll
+    for (int grp = 0; grp < 3; ++grp) {
+      const Rsrc rs = rsrc(src + uint64_t(wrap(p - (grp - 1), k.n2)) * k.slab_bytes);
+      const uint32_t so = 9u * grp * sb;
+      g.a[grp] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[0], so, 0);
+      g.b[grp] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[1], so, 0);
+      g.pr[grp] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff[2], so, 0);
+    }
+  };
+  auto stage_store = [&](unsigned char* stg, const Staged& g) {
+#pragma unroll
+    for (int grp = 0; grp < 3; ++grp) {
+      *reinterpret_cast<u32x4*>(stg + 9 * grp * BOX + loff[0]) = g.a[grp];
+      *reinterpret_cast<u32x4*>(stg + 9 * grp * BOX + loff[1]) = g.b[grp];
+      *reinterpret_cast<uint32_t*>(stg + 9 * grp * BOX + loff[2]) = g.pr[grp];
+    }
+  };
+
+  // next-plane anomaly of the node (ring) and of its halo node, from stage stg
+  float drho, dj[3], qc[3] = {0.f, 0.f, 0.f}, qprev;
+  auto plane_anomalies = [&](const unsigned char* stg, int bo, float& dr, float (&djo)[3], float (&q)[3]) {
+    moments(stg, rb, dr, djo);
+    const float ir = recip(1.f + dr);
+    q[0] = anomaly(k, 0, djo[0], ir);
+    q[1] = anomaly(k, 1, djo[1], ir);
+    q[2] = anomaly(k, 2, djo[2], ir);
+    if (has_halo) {
+      float hr, hj[3];
+      moments(stg, hb, hr, hj);
+      const float j = h_uref + (hax == 0 ? hj[0] : hj[1]);
+      const float u = j * recip(1.f + hr);
+      anom[hofs + bo * hstep + hslot] = j * h_anom - j * u * u;
+    }
+  };
+  auto plane_index = [&](int zz) {
+    while (zz >= k.n2) zz -= k.n2;
+    return zz < 0 ? zz + k.n2 : zz;
+  };
+
+  // ---- prologue: the ring plane z0 - 1 and plane z0 ----
+  int bz, bz1, bfree = 0;
+  {
+    Staged g;
+    stage_load(plane_index(z0 - 1), sb0, g);
+    stage_store(smem, g);
+    stage_load(z0, sb0, g);
+    stage_store(smem + STAGE, g);
+    __syncthreads();
+    float dr, djp[3];
+    moments(smem, rb, dr, djp);
+    qprev = anomaly(k, 2, djp[2], recip(1.f + dr));
+    plane_anomalies(smem + STAGE, 0, drho, dj, qc);
+    QX(0, sx_own) = qc[0];
+    QY(0, sy_own) = qc[1];
+    if (NSTAGE == 3) {
+      stage_load(plane_index(z0 + 1), sb0, g);
+      stage_store(smem + 2 * STAGE, g);
+      bz = 1, bz1 = 2, bfree = 0;
+    } else {
+      __syncthreads();  // plane z0 - 1's buffer is read
+      stage_load(plane_index(z0 + 1), sb0, g);
+      stage_store(smem, g);
+      bz = 1, bz1 = 0;
+    }
+  }
+  __syncthreads();
+
+  for (int z = z0; z < z1; ++z) {
+    const int b = (z - z0) & 1;
+    // the array distance is made opaque per plane (see the kernel above)
+    uint32_t sb = sb0;
+    asm("" : "+s"(sb) : "s"(z));
+    // stage of plane z + 2: its loads fly while this plane is updated
+    Staged g;
+    stage_load(plane_index(z + 2), sb, g);
+    const unsigned char* s_z = smem + bz * STAGE;
+
+    // next plane: own anomaly (closes the ring) and the halo's
+    float drn, djn[3], qn[3];
+    plane_anomalies(smem + bz1 * STAGE, b ^ 1, drn, djn, qn);
+
+    // collision of plane z
+    {
+      float Gd[3];
+      Gd[0] = (QX(b, sxp) - QX(b, sxm)) * k.hil[0];
+      Gd[1] = (QY(b, syp) - QY(b, sym)) * k.hil[1];
+      Gd[2] = (qn[2] - qprev) * k.hil[2];
+      const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
+      const uint32_t own = uint32_t(gy * k.n0 + gx) * 2u;
+      collide<3, FORCE>(k, drho, dj, Gd, [&](int i) { return Store<S>::to_float(pull_lds(s_z, rb, i)); },
+                        [&](int i, float o) { Store<S>::store(rd, own, i * sb, o); });
+    }
+    QX(b ^ 1, sx_own) = qn[0];
+    QY(b ^ 1, sy_own) = qn[1];
+    if (NSTAGE == 3) {
+      // into plane z - 1's buffer, free since the last barrier
+      stage_store(smem + bfree * STAGE, g);
+      __syncthreads();
+      const int t = bz;
+      bz = bz1;
+      bz1 = bfree;
+      bfree = t;
+    } else {
+      // into plane z's buffer, once every thread has relaxed plane z
+      __syncthreads();
+      stage_store(smem + bz * STAGE, g);
+      __syncthreads();
+      const int t = bz;
+      bz = bz1;
+      bz1 = t;
+    }
+    drho = drn;
+    dj[0] = djn[0];
+    dj[1] = djn[1];
+    dj[2] = djn[2];
+    qprev = qc[2];
+    qc[0] = qn[0];
+    qc[1] = qn[1];
+    qc[2] = qn[2];
+  }
+}
+
+template <int S, bool FORCE>
+__global__ void __launch_bounds__(lds::NT)
+    step_kernel_lds(const TableHeader* __restrict__ hdr, const LatticeDesc* __restrict__ table, int64_t substep) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[lds::BYTES];
+  const int64_t total = hdr->total_tiles;
+  const int count = hdr->count;
+  const int gpx = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int lb = blockIdx.x >> 3;
+  const int64_t per = (total + 7) >> 3;
+  const int64_t tb = xcd * per;
+  const int64_t te = min(tb + per, total);
+  int L = 0;
+  for (int64_t t = tb + lb; t < te; t += gpx) {
+    while (L + 1 < count && table[L + 1].tile_base <= t) ++L;
+    const LatticeDesc* d = table + L;
+    if (substep < d->nsteps) {
+      const int parity = (d->parity0 + int(substep & 1)) & 1;
+      step_tile_lds<S, FORCE>(d, t - d->tile_base, parity, smem);
+    }
+    __syncthreads();
   }
 }
 
@@ -695,6 +1034,12 @@ hipError_t launch_ds(bool wall, bool force, const TableHeader* hdr, const Lattic
                : launch_one<D, S, false, false>(hdr, table, s, grid, st);
 }
 
+template <int S, bool FORCE>
+hipError_t launch_lds(const TableHeader* hdr, const LatticeDesc* table, int64_t substep, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((step_kernel_lds<S, FORCE>), dim3(grid), dim3(lds::NT), 0, st, hdr, table, substep);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int step_block_threads(int D) { return D == 3 ? Geo<3, 0>::NT : Geo<2, 0>::NT; }
@@ -708,13 +1053,24 @@ int occupancy_one() {
   return n > 0 ? n : 1;
 }
 
+template <int S, bool FORCE>
+int occupancy_lds() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_lds<S, FORCE>, lds::NT, 0) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
+
 template <int D, int S>
 int occupancy_ds(bool wall, bool force) {
   if (wall) return force ? occupancy_one<D, S, true, true>() : occupancy_one<D, S, true, false>();
   return force ? occupancy_one<D, S, false, true>() : occupancy_one<D, S, false, false>();
 }
 
-int step_blocks_per_cu(int D, int storage, bool wall, bool force) {
+int step_blocks_per_cu(int D, int storage, bool wall, bool force, bool staged) {
+  if (staged && D == 3 && !wall && storage != 0) {
+    if (storage == 1) return force ? occupancy_lds<1, true>() : occupancy_lds<1, false>();
+    return force ? occupancy_lds<2, true>() : occupancy_lds<2, false>();
+  }
   if (D == 3) {
     switch (storage) {
       case 0: return occupancy_ds<3, 0>(wall, force);
@@ -729,9 +1085,16 @@ int step_blocks_per_cu(int D, int storage, bool wall, bool force) {
   }
 }
 
-hipError_t launch_step(int D, int storage, bool wall, bool force, const TableHeader* hdr,
+hipError_t launch_step(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
                        const LatticeDesc* table, int64_t substep, int grid, hipStream_t st) {
   if (grid <= 0 || (grid & 7)) return hipErrorInvalidConfiguration;
+  if (staged) {
+    if (D != 3 || wall || (storage != 1 && storage != 2)) return hipErrorInvalidValue;
+    if (storage == 1) return force ? launch_lds<1, true>(hdr, table, substep, grid, st)
+                                   : launch_lds<1, false>(hdr, table, substep, grid, st);
+    return force ? launch_lds<2, true>(hdr, table, substep, grid, st)
+                 : launch_lds<2, false>(hdr, table, substep, grid, st);
+  }
   if (D == 3) {
     switch (storage) {
       case 0: return launch_ds<3, 0>(wall, force, hdr, table, substep, grid, st);

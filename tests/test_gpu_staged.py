@@ -1,0 +1,73 @@
+"""The LDS-staged D3Q27 step kernel (16-bit storage, periodic lattices whose
+n_x is a multiple of 64 and n_y a multiple of 8).
+
+It pulls the same stored values as the register-pull kernel and runs the same
+per-node arithmetic, so the two agree bitwise; against the FP64 oracle one
+step from an arbitrary state is held to the storage rounding: half an ulp of
+the largest stored deviation, at most its unit roundoff times it (2^-11 for
+FP16, 2^-8 for BF16), plus the FP32 arithmetic bound of the single-precision
+tests.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_helpers import dev_rel_l2, lib, params_for, random_state
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "cube64": dict(n=(64, 64, 64), T=0.5, omega=1.89),
+    "flat_force_stretched": dict(n=(128, 16, 12), lam=(2.0, 1.0, 1.0), T=0.4, omega=1.6,
+                                 force=(1e-4, -5e-5, 2e-5)),
+    "three_planes": dict(n=(64, 8, 3), T=1 / 3, omega=1.2),
+}
+EPS = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+def lattice(p, storage, staged, f0):
+    E = lib()
+    old = os.environ.get("ELBM_STAGED")
+    os.environ["ELBM_STAGED"] = "1" if staged else "0"
+    try:
+        lat = E.Lattice(params_for(p, storage))
+    finally:
+        if old is None:
+            del os.environ["ELBM_STAGED"]
+        else:
+            os.environ["ELBM_STAGED"] = old
+    lat.set_populations(f0)
+    return lat
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_staged_equals_register_pull_bitwise(case, storage):
+    p = O.Params(**CASES[case])
+    f0 = random_state(p, seed=7)
+    a = lattice(p, storage, True, f0)
+    b = lattice(p, storage, False, f0)
+    a.step(7)
+    b.step(7)
+    assert np.array_equal(a.save(), b.save()), (case, storage)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_staged_one_step_against_oracle(case, storage):
+    p = O.Params(**CASES[case])
+    f0 = random_state(p, seed=11)
+    lat = lattice(p, storage, True, f0)
+    g0 = lat.populations()  # the stored (rounded) initial state
+    lat.step(1)
+    g1 = lat.populations()
+    o1 = O.step(g0, p)
+    w = O.reference_weights(p).reshape((-1,) + (1,) * p.D)
+    hmax = float(np.abs(o1 - w).max())
+    assert np.abs(g1 - o1).max() <= EPS[storage] * hmax * 1.05 + 2e-7, case
+    assert dev_rel_l2(g1, o1, p) <= EPS[storage], case
+    lat.close()
