@@ -240,38 +240,49 @@ __global__ void __launch_bounds__(kDiagThreads)
   }
 }
 
-// Central difference of velocity component comp along axis b at node (x,y,z),
-// spacing lambda_b; periodic wrap, or the no-slip ghost u(-1) = -u(0) on a
-// wall axis.
-__device__ __forceinline__ double dudx(const LatticeConst64& c, const float* u, int comp, int b, int x, int y, int z) {
-  const int n = c.n[b];
-  const int p[3] = {x, y, z};
-  const int64_t own = x + int64_t(c.n[0]) * (y + int64_t(c.n[1]) * z);
-  const double uo = u[comp * c.N + own];
-  const int64_t st = b == 0 ? 1 : (b == 1 ? c.n[0] : int64_t(c.n[0]) * c.n[1]);
-  double up, um;
-  if (p[b] + 1 < n) up = u[comp * c.N + own + st];
-  else up = c.wall[b] ? -uo : u[comp * c.N + own - (n - 1) * st];
-  if (p[b] > 0) um = u[comp * c.N + own - st];
-  else um = c.wall[b] ? -uo : u[comp * c.N + own + (n - 1) * st];
-  return (up - um) / (2.0 * c.lam[b]);
+// Central difference of velocity component comp along axis b at the node of
+// linear index `own` and coordinate pb along b (stride st, extent n), times
+// 1 / (2 lambda_b) = h; periodic wrap, or the no-slip ghost u(-1) = -u(0) on a
+// wall axis. FP32: the staged velocities are FP32 already, and one rounding
+// of the difference keeps ~1e-7 relative accuracy per node.
+__device__ __forceinline__ float dudx(const LatticeConst64& c, const float* __restrict__ u, int comp, int b, int pb,
+                                      int n, int64_t own, int64_t st, float h) {
+  const float* uc = u + comp * c.N;
+  const float uo = uc[own];
+  float up, um;
+  if (pb + 1 < n) up = uc[own + st];
+  else up = c.wall[b] ? -uo : uc[own - (n - 1) * st];
+  if (pb > 0) um = uc[own - st];
+  else um = c.wall[b] ? -uo : uc[own + (n - 1) * st];
+  return (up - um) * h;
 }
 
+// Enstrophy partial sums: a block takes whole x rows (grid-strided over the
+// rows), its threads the nodes of a row, so that coordinates come from one
+// 32-bit division per row and every read is a coalesced row segment. The
+// vorticity of a node is formed in FP32, its square accumulated in FP64.
 __global__ void __launch_bounds__(kDiagThreads)
     diag_curl_kernel(LatticeConst64 c, const float* __restrict__ ustage, double* __restrict__ partials) {
   __shared__ double sh[kDiagThreads / 64];
   double ens = 0.0;
-  const int nx = c.n[0], ny = c.n[1];
-  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < c.N; k += int64_t(gridDim.x) * blockDim.x) {
-    const int x = int(k % nx), y = int((k / nx) % ny), z = int(k / (int64_t(nx) * ny));
-    if (c.D == 2) {
-      const double wz = dudx(c, ustage, 1, 0, x, y, z) - dudx(c, ustage, 0, 1, x, y, z);
-      ens += wz * wz;
-    } else {
-      const double wx = dudx(c, ustage, 2, 1, x, y, z) - dudx(c, ustage, 1, 2, x, y, z);
-      const double wy = dudx(c, ustage, 0, 2, x, y, z) - dudx(c, ustage, 2, 0, x, y, z);
-      const double wz = dudx(c, ustage, 1, 0, x, y, z) - dudx(c, ustage, 0, 1, x, y, z);
-      ens += wx * wx + wy * wy + wz * wz;
+  const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
+  const int64_t sy = nx, sz = int64_t(nx) * ny;
+  const float h0 = float(0.5 / c.lam[0]), h1 = float(0.5 / c.lam[1]), h2 = float(0.5 / c.lam[2]);
+  const int rows = ny * nz;
+  for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int y = r % ny, z = r / ny;
+    const int64_t row = sy * y + sz * z;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+      const int64_t own = row + x;
+      if (c.D == 2) {
+        const float wz = dudx(c, ustage, 1, 0, x, nx, own, 1, h0) - dudx(c, ustage, 0, 1, y, ny, own, sy, h1);
+        ens += double(wz * wz);
+      } else {
+        const float wx = dudx(c, ustage, 2, 1, y, ny, own, sy, h1) - dudx(c, ustage, 1, 2, z, nz, own, sz, h2);
+        const float wy = dudx(c, ustage, 0, 2, z, nz, own, sz, h2) - dudx(c, ustage, 2, 0, x, nx, own, 1, h0);
+        const float wz = dudx(c, ustage, 1, 0, x, nx, own, 1, h0) - dudx(c, ustage, 0, 1, y, ny, own, sy, h1);
+        ens += double(wx * wx + wy * wy + wz * wz);
+      }
     }
   }
   const double r = block_reduce(ens, 0, sh);
