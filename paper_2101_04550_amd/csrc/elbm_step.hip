@@ -812,10 +812,14 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
   };
 
   // ---- staging: this thread's loads (fixed along the march) ----
-  // Interior chunks a and b (the second clamped into range: a duplicate load
-  // stores the same bytes twice) and one side pair, per c_z group; group g
-  // covers directions 9 g ... 9 g + 8, i.e. array j of the group is direction
-  // 9 g + j, so group g adds 9 g arrays to both offsets.
+  // Interior chunks a and b and one side pair, per c_z group; group g covers
+  // directions 9 g ... 9 g + 8, i.e. array j of the group is direction 9 g + j,
+  // so group g adds 9 g arrays to both offsets. Chunk b and the pair are
+  // issued only by the waves that hold such items (a wave-uniform test);
+  // within the last of those waves the spare lanes repeat the final item.
+  static_assert(CHUNKS >= NT, "every thread stages an interior chunk a");
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool wave_b = wave * 64 < CHUNKS - NT, wave_p = wave * 64 < PAIRS;
   uint32_t voff[3];
   int loff[3];
   {
@@ -850,16 +854,16 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
       const Rsrc rs = rsrc(src + uint64_t(wrap(p - (grp - 1), k.n2)) * k.slab_bytes);
       const uint32_t so = 9u * grp * sb;
       g.a[grp] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[0], so, 0);
-      g.b[grp] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[1], so, 0);
-      g.pr[grp] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff[2], so, 0);
+      if (wave_b) g.b[grp] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[1], so, 0);
+      if (wave_p) g.pr[grp] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff[2], so, 0);
     }
   };
   auto stage_store = [&](unsigned char* stg, const Staged& g) {
 #pragma unroll
     for (int grp = 0; grp < 3; ++grp) {
       *reinterpret_cast<u32x4*>(stg + 9 * grp * BOX + loff[0]) = g.a[grp];
-      *reinterpret_cast<u32x4*>(stg + 9 * grp * BOX + loff[1]) = g.b[grp];
-      *reinterpret_cast<uint32_t*>(stg + 9 * grp * BOX + loff[2]) = g.pr[grp];
+      if (wave_b) *reinterpret_cast<u32x4*>(stg + 9 * grp * BOX + loff[1]) = g.b[grp];
+      if (wave_p) *reinterpret_cast<uint32_t*>(stg + 9 * grp * BOX + loff[2]) = g.pr[grp];
     }
   };
 
