@@ -26,6 +26,14 @@ def _mix():
     out.append((p, I.hit_field(48, k0=4.0, urms=0.05, seed_offset=12), "bf16"))
     p = O.Params(n=(96, 64, 40), T=0.5, omega=1.6)
     out.append((p, I.uniform((96, 64, 40), u0=(0.02, 0.0, -0.01)), "f32"))
+    # LDS-staged kernel class (16-bit, periodic, n_x % 64 == 0, n_y % 16 == 0):
+    # two lattices in one table, and the forced variant
+    p = O.Params(n=(64, 32, 24), T=0.5, omega=1.85)
+    out.append((p, I.channel_field((64, 32, 24), (1.0, 1.0, 1.0), seed_offset=13), "f16"))
+    p = O.Params(n=(128, 16, 12), lam=(2.0, 1.0, 1.0), T=0.4, omega=1.6)
+    out.append((p, I.uniform((128, 16, 12), u0=(0.01, -0.02, 0.005)), "f16"))
+    p = O.Params(n=(64, 16, 20), T=1 / 3, omega=1.3, force=(1e-4, -2e-4, 5e-5))
+    out.append((p, I.uniform((64, 16, 20), u0=(0.0, 0.01, 0.0)), "bf16"))
     return out
 
 
@@ -37,7 +45,7 @@ def _make(mix):
 def test_batch_equals_alone_bitwise(use_graph):
     E = lib()
     mix = _mix()
-    steps = [7, 12, 3, 12, 9, 1]
+    steps = [7, 12, 3, 12, 9, 1, 5, 12, 8]
     alone = _make(mix)
     for lat, k in zip(alone, steps):
         lat.step(k)
@@ -56,7 +64,7 @@ def test_graph_reuse_across_mixes_and_continuation():
     run followed by solo steps continues the same trajectory."""
     E = lib()
     mix = _mix()
-    total = [20, 20, 20, 20, 20, 20]
+    total = [20] * 9
     alone = _make(mix)
     for lat, k in zip(alone, total):
         lat.step(k)
@@ -64,8 +72,8 @@ def test_graph_reuse_across_mixes_and_continuation():
     lats = _make(mix)
     b = E.Batch(len(lats))
     # three rounds of at most 8 steps; lattices drop in and out of the mix
-    b.run(lats, [8, 8, 0, 8, 3, 8], use_graph=True)
-    b.run(lats, [8, 5, 8, 8, 8, 8], use_graph=True)
+    b.run(lats, [8, 8, 0, 8, 3, 8, 8, 0, 5], use_graph=True)
+    b.run(lats, [8, 5, 8, 8, 8, 8, 8, 8, 8], use_graph=True)
     done = [lat.step_count for lat in lats]
     b.run(lats[::-1], [min(8, 20 - d) for d in done[::-1]], use_graph=True)
     for lat in lats:
