@@ -104,6 +104,7 @@ def run_gpu(storage, fld, steps, warmup, kernel_reps):
                            diag_capacity=max(1, (steps + warmup) // DIAG_EVERY + 1))
     lat = E.Lattice(params)
     lat.init(fld.rho, fld.u)
+    info = lat.kernel_info()
     stream = lat.stream
     lat.step(warmup)
     lat.sync()
@@ -151,6 +152,7 @@ def run_gpu(storage, fld, steps, warmup, kernel_reps):
         "ke_last": hist[-1]["ke"] if hist else None,
         "enstrophy_last": hist[-1]["enstrophy"] if hist else None,
         "final_min_rho": d["min_rho"],
+        "kernel": info,
     }
 
 
@@ -307,7 +309,10 @@ def main():
         "storage_variants": {
             s: {"mlups": round(r["mlups"], 1), "kernel_ms": round(r["kernel_ms"], 5),
                 "kernel_gbs": round(r["kernel_gbs"], 1),
-                "vs_f32": round(r["mlups"] / main_run["mlups"], 3)}
+                "vs_f32": round(r["mlups"] / main_run["mlups"], 3),
+                "kernel": "step_kernel_lds (LDS staged)" if r["kernel"]["kernel"] == "staged"
+                else "step_kernel (register pull)",
+                "block_threads": r["kernel"]["block_threads"], "tile": list(r["kernel"]["tile"])}
             for s, r in runs.items()
         },
         "diagnostics": {s: {"ke_first": r["ke_first"], "ke_last": r["ke_last"],

@@ -128,6 +128,20 @@ typedef struct elbm_diag_record {
   int64_t nan_count;
 } elbm_diag_record;
 
+/* How the library advances a lattice (inspection and measurement). */
+enum { ELBM_KERNEL_REGISTER = 0, ELBM_KERNEL_STAGED = 1 };
+typedef struct elbm_kernel_info {
+  int32_t kernel;         /* ELBM_KERNEL_REGISTER: each node pulls its Q values
+                             with one load apiece; ELBM_KERNEL_STAGED: a block
+                             stages the rows its tile pulls from in LDS (periodic
+                             D3Q27 with 16-bit storage, n_x % 64 == 0, n_y % 16 == 0) */
+  int32_t block_threads;  /* threads per workgroup */
+  int32_t tile[3];        /* tile extent along the internal axes: x, y (1 for
+                             D2Q9), and the planes marched per tile */
+  int32_t blocks_per_cu;  /* resident workgroups per compute unit */
+  int64_t tiles;          /* tiles per step (workgroup tasks) */
+} elbm_kernel_info;
+
 typedef struct elbm_lattice* elbm_handle;
 typedef struct elbm_batch_s* elbm_batch;
 
@@ -181,6 +195,11 @@ int32_t elbm_step(elbm_handle h, int64_t nsteps);
 
 /* Number of steps taken since elbm_init / elbm_set_populations. */
 int64_t elbm_step_count(elbm_handle h);
+
+/* The step kernel and launch shape chosen for this lattice (fixed at
+ * elbm_create; the environment variable ELBM_STAGED=0 forces the register
+ * kernel). ELBM_EINVAL on NULL arguments. Host only. */
+int32_t elbm_kernel(elbm_handle h, elbm_kernel_info* out);
 
 /* Macroscopic fields of the current state, FP64, host arrays owned by the
  * caller: rho[N], u[D * N] (component-major), u = (j + rho g/2)/rho.

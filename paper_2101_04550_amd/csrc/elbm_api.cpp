@@ -509,6 +509,20 @@ int32_t elbm_step(elbm_handle h, int64_t nsteps) {
 
 int64_t elbm_step_count(elbm_handle h) { return h ? h->step : -1; }
 
+int32_t elbm_kernel(elbm_handle h, elbm_kernel_info* out) {
+  if (!h || !out) return fail(ELBM_EINVAL, "NULL argument");
+  elbm_kernel_info k{};
+  k.kernel = h->staged ? ELBM_KERNEL_STAGED : ELBM_KERNEL_REGISTER;
+  k.block_threads = step_block_threads(h->D, h->staged);
+  k.tile[0] = h->D == 3 ? (h->staged ? 64 : kTileX3) : 64 * kStrips2;
+  k.tile[1] = h->D == 3 ? (h->staged ? kRowsStaged : kRows3) : 1;
+  k.tile[2] = h->desc.chunk;
+  k.blocks_per_cu = step_blocks_per_cu(h->D, h->p.storage, h->wall, h->force, h->staged);
+  k.tiles = h->ntiles;
+  *out = k;
+  return ELBM_OK;
+}
+
 int32_t elbm_fields(elbm_handle h, double* rho, double* u) {
   if (!h || !rho || !u) return fail(ELBM_EINVAL, "NULL argument");
   int32_t s = set_dev(h->device);

@@ -116,7 +116,7 @@ struct LatticeConst64 {
 // staged: the LDS-staged D3Q27 kernel for 16-bit storage (periodic, full tiles).
 hipError_t launch_step(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
                        const LatticeDesc* table, int64_t substep, int grid, hipStream_t st);
-int step_block_threads(int D);
+int step_block_threads(int D, bool staged);
 // Resident step blocks per compute unit for a kernel class (occupancy query).
 int step_blocks_per_cu(int D, int storage, bool wall, bool force, bool staged);
 

@@ -1046,7 +1046,7 @@ hipError_t launch_lds(const TableHeader* hdr, const LatticeDesc* table, int64_t 
 
 }  // namespace
 
-int step_block_threads(int D) { return D == 3 ? Geo<3, 0>::NT : Geo<2, 0>::NT; }
+int step_block_threads(int D, bool staged) { return staged ? lds::NT : (D == 3 ? Geo<3, 0>::NT : Geo<2, 0>::NT); }
 
 template <int D, int S, bool WALL, bool FORCE>
 int occupancy_one() {

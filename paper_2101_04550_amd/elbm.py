@@ -56,6 +56,16 @@ class ElbmParams(C.Structure):
     ]
 
 
+class ElbmKernelInfo(C.Structure):
+    _fields_ = [
+        ("kernel", C.c_int32),
+        ("block_threads", C.c_int32),
+        ("tile", C.c_int32 * 3),
+        ("blocks_per_cu", C.c_int32),
+        ("tiles", C.c_int64),
+    ]
+
+
 class ElbmDiag(C.Structure):
     _fields_ = [
         ("step", C.c_int64),
@@ -89,6 +99,7 @@ _sigs = {
     "elbm_init": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "elbm_step": (C.c_int32, [C.c_void_p, C.c_int64]),
     "elbm_step_count": (C.c_int64, [C.c_void_p]),
+    "elbm_kernel": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "elbm_fields": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "elbm_populations": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "elbm_set_populations": (C.c_int32, [C.c_void_p, C.c_void_p]),
@@ -220,6 +231,13 @@ class Lattice:
     @property
     def step_count(self):
         return int(_lib.elbm_step_count(self.handle))
+
+    def kernel_info(self):
+        """The step kernel and launch shape chosen for this lattice."""
+        k = ElbmKernelInfo()
+        _check(_lib.elbm_kernel(self.handle, C.byref(k)), "elbm_kernel")
+        return {"kernel": "staged" if k.kernel == 1 else "register", "block_threads": k.block_threads,
+                "tile": tuple(k.tile), "blocks_per_cu": k.blocks_per_cu, "tiles": k.tiles}
 
     def fields(self):
         rho = np.empty(self.N)

@@ -22,8 +22,10 @@ CASES = {
     "cube64": dict(n=(64, 64, 64), T=0.5, omega=1.89),
     "flat_force_stretched": dict(n=(128, 16, 12), lam=(2.0, 1.0, 1.0), T=0.4, omega=1.6,
                                  force=(1e-4, -5e-5, 2e-5)),
-    "three_planes": dict(n=(64, 8, 3), T=1 / 3, omega=1.2),
+    "three_planes": dict(n=(64, 16, 3), T=1 / 3, omega=1.2),
 }
+# not eligible (n_y % 16 != 0): takes the register-pull kernel
+RAGGED = dict(n=(64, 8, 5), T=0.5, omega=1.5)
 EPS = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
 
 
@@ -49,6 +51,9 @@ def test_staged_equals_register_pull_bitwise(case, storage):
     f0 = random_state(p, seed=7)
     a = lattice(p, storage, True, f0)
     b = lattice(p, storage, False, f0)
+    assert a.kernel_info()["kernel"] == "staged"
+    assert a.kernel_info()["block_threads"] == 1024
+    assert b.kernel_info()["kernel"] == "register"
     a.step(7)
     b.step(7)
     assert np.array_equal(a.save(), b.save()), (case, storage)
@@ -70,4 +75,16 @@ def test_staged_one_step_against_oracle(case, storage):
     hmax = float(np.abs(o1 - w).max())
     assert np.abs(g1 - o1).max() <= EPS[storage] * hmax * 1.05 + 2e-7, case
     assert dev_rel_l2(g1, o1, p) <= EPS[storage], case
+    lat.close()
+
+
+def test_kernel_choice():
+    p = O.Params(**RAGGED)
+    lat = lattice(p, "f16", True, random_state(p, seed=3))
+    assert lat.kernel_info()["kernel"] == "register"
+    lat.close()
+    p = O.Params(**CASES["cube64"])
+    lat = lattice(p, "f32", True, random_state(p, seed=3))
+    info = lat.kernel_info()
+    assert info["kernel"] == "register" and info["tile"][:2] == (64, 8) and info["tiles"] >= 1
     lat.close()
