@@ -211,6 +211,45 @@ def d2q9_leg(n=1024, steps=2000):
     return out
 
 
+def channel_leg(steps=300):
+    """D3Q27 channel on the stretched lattice (dy/dx = 0.5): 384 x 192 x 192,
+    bounce-back walls in y, body force for Re_tau = 180, T = 0.5,
+    omega = 1.976785; FP32 and FP16 storage, step rate after 20 warm-up steps
+    (the workload's 5000-step run is the same kernel)."""
+    import torch
+
+    import inputs as I
+    from paper_2101_04550_amd import elbm as E
+
+    n, lam, omega = (384, 192, 192), (2.0, 1.0, 1.0), 1.976785
+    nu = (1 / omega - 0.5) * 0.5
+    g = 180.0 ** 2 * nu ** 2 / 96.0 ** 3
+    fld = I.channel_field(n, lam)
+    N = math.prod(n)
+    out = {}
+    for st in ("f32", "f16"):
+        lat = E.Lattice(E.make_params(n, lam=lam, T=0.5, omega=omega, walls=(False, True, False),
+                                      force=(g, 0.0, 0.0), storage=st))
+        lat.init(fld.rho, fld.u)
+        info = lat.kernel_info()
+        lat.step(20)
+        lat.sync()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(lat.stream)
+        lat.step(steps)
+        b.record(lat.stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / steps
+        es = 4 if st == "f32" else 2
+        out[st] = {"mlups": round(N / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 5),
+                   "alg_gbs": round(2 * 27 * es * N / (ms * 1e-3) / 1e9, 1), "kernel": info["kernel"]}
+        lat.close()
+    torch.cuda.empty_cache()
+    out["note"] = "D3Q27 channel 384x192x192, lambda = (2, 1, 1), walls in y, Re_tau = 180 force"
+    return out
+
+
 def cpu_baseline(seconds_budget=20.0):
     """The FP64 NumPy oracle (untuned) on a bounded sample of the same workload:
     a 96^3 box of the same spectrum (k0 = 4), timed over whole steps."""
@@ -321,6 +360,7 @@ def main():
     }
     if args.n == N_HIT and not args.hit_only:
         out["d2q9"] = d2q9_leg()
+        out["channel"] = channel_leg()
     if args.serve_requests > 0 and args.n == N_HIT and not args.hit_only:
         out["serving"] = serving_leg(args.serve_requests)
         print(f"# serving: {out['serving']['solves_per_s']:.1f} solves/s, p50 {out['serving']['p50_latency_s']:.3f} s, "

@@ -1,4 +1,4 @@
-// Fused extended-LBGK step kernel for gfx950.
+// Fused extended-LBGK step kernels for gfx950.
 //
 // One launch advances every tile of every lattice in a descriptor table by one
 // time step (Sec. 2.1, eq. LBGK). Per node the kernel
@@ -17,15 +17,25 @@
 //
 // Layout and schedule
 // -------------------
-// Populations are Q structure-of-arrays arrays (x fastest), two buffers
-// (ping-pong). A block owns a tile of 64 x 8 nodes of the x-y plane (D3Q27)
-// or a 256-node x strip (D2Q9) and marches along the slowest axis (z, resp.
-// y) over `chunk` planes. The anomaly of the marched axis comes from a
-// three-plane register ring (previous, current, next); the anomalies of the
-// tiled axes go through LDS, double buffered by plane, with a one-node cross
-// halo whose nodes are pulled by the first threads of the block. Each plane
-// costs one HBM read and one HBM write of every population of its nodes;
-// halo and ring-end pulls re-read data neighbouring tiles also read (L2).
+// Populations are stored in plane slabs along the slowest axis (plane z: Q
+// direction arrays of the plane's nodes, x fastest), two buffers (ping-pong).
+// A block owns a tile of the x-y plane (D3Q27) or an x strip (D2Q9) and
+// marches along the slowest axis (z, resp. y) over `chunk` planes. The
+// anomaly of the marched axis comes from a three-plane register ring
+// (previous, current, next); the anomalies of the tiled axes go through LDS,
+// double buffered by plane, with a one-node cross halo whose nodes are
+// pulled by the first threads of the block. Each plane costs one HBM read
+// and one HBM write of every population of its nodes; halo and ring-end pulls
+// re-read data neighbouring tiles also read (L2).
+//
+// Two kernels implement the march:
+//   step_kernel     -- register pull: a thread loads each of its node's Q
+//                      values with one buffer load (64 x 8 tiles, 512 threads;
+//                      D2Q9 strips of 256); every lattice class.
+//   step_kernel_lds -- LDS staged (16-bit storage, periodic D3Q27, full 64 x 16
+//                      tiles, 1024 threads): the block stages the rows its
+//                      tile pulls from with 16-byte loads and pulls from LDS.
+// Both run the same per-node arithmetic (collide) on the same stored values.
 //
 // Arithmetic is FP32 on deviations h_i = f_i - w_i from the reference
 // equilibrium w_i = prod_a W_a[c_ia] (rho = 1, u = u_ref). Moments,
@@ -44,7 +54,6 @@
 #include <hip/hip_fp16.h>
 
 #include "elbm_internal.h"
-
 
 namespace elbm {
 namespace {
@@ -212,16 +221,28 @@ struct Puller {
   // own post-collision population of the opposite direction.
   __device__ static __forceinline__ void fetch(uint32_t sb, const PlaneSrc& ps, const NodeOffs& no, bool near,
                                                Pops<S, Q>& h) {
+    if (WALL && near) {
+      // all loads first, then the per-lane choices (a choice right after its
+      // own loads would make each direction wait for them in turn)
+      R bb[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int c0 = cq<D>(i, 0), c1 = cq<D>(i, 1), c2 = cq<D>(i, 2);
-      R raw = Store<S>::load(ps.r[c2 + 1], no.o[c0 + 1][c1 + 1], i * sb);
-      if (WALL && i != Q / 2 && near) {
-        const R bb = Store<S>::load(ps.r[1], no.own, (Q - 1 - i) * sb);
-        const bool out = (c0 != 0 && no.ox[c0 + 1]) || (c1 != 0 && no.oy[c1 + 1]) || (c2 != 0 && ps.oz[c2 + 1]);
-        raw = out ? bb : raw;
+      for (int i = 0; i < Q; ++i) {
+        const int c0 = cq<D>(i, 0), c1 = cq<D>(i, 1), c2 = cq<D>(i, 2);
+        h.v[i] = Store<S>::load(ps.r[c2 + 1], no.o[c0 + 1][c1 + 1], i * sb);
+        bb[i] = i == Q / 2 ? h.v[i] : Store<S>::load(ps.r[1], no.own, (Q - 1 - i) * sb);
       }
-      h.v[i] = raw;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int c0 = cq<D>(i, 0), c1 = cq<D>(i, 1), c2 = cq<D>(i, 2);
+        const bool out = (c0 != 0 && no.ox[c0 + 1]) || (c1 != 0 && no.oy[c1 + 1]) || (c2 != 0 && ps.oz[c2 + 1]);
+        h.v[i] = out ? bb[i] : h.v[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int c0 = cq<D>(i, 0), c1 = cq<D>(i, 1), c2 = cq<D>(i, 2);
+        h.v[i] = Store<S>::load(ps.r[c2 + 1], no.o[c0 + 1][c1 + 1], i * sb);
+      }
     }
   }
 
