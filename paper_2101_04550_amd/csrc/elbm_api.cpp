@@ -85,13 +85,15 @@ int class_of(int D, int storage, bool wall, bool force, bool staged) {
   return ((((D == 3) * 3 + storage) * 2 + (wall ? 1 : 0)) * 2 + (force ? 1 : 0)) * 2 + (staged ? 1 : 0);
 }
 
-// Whether a lattice takes the LDS-staged step kernel: periodic D3Q27 with
-// 16-bit storage and full tiles (n_x % 64 == 0, n_y % kRowsStaged == 0).
-// ELBM_STAGED=0 forces the register-pull kernel (for measurements).
-bool use_staged(const elbm_params& p, bool wall) {
+// Whether a lattice takes the LDS-staged step kernel: D3Q27 with 16-bit
+// storage, full tiles (n_x % 64 == 0, n_y % kRowsStaged == 0), x and z
+// periodic, y periodic or bounce-back. ELBM_STAGED=0 forces the register-pull
+// kernel (for measurements).
+bool use_staged(const elbm_params& p) {
   if (const char* s = std::getenv("ELBM_STAGED"))
     if (s[0] == '0') return false;
-  return p.lattice == 27 && p.storage != ELBM_STORE_F32 && !wall && p.n[0] % 64 == 0 && p.n[1] % kRowsStaged == 0;
+  return p.lattice == 27 && p.storage != ELBM_STORE_F32 && p.bc[0] == ELBM_BC_PERIODIC &&
+         p.bc[2] == ELBM_BC_PERIODIC && p.n[0] % 64 == 0 && p.n[1] % kRowsStaged == 0;
 }
 
 bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
@@ -437,7 +439,7 @@ int32_t elbm_create(const elbm_params* p, void* dev_buf, size_t bytes, void* hip
   h->wall = false;
   for (int a = 0; a < h->D; ++a) h->wall = h->wall || p->bc[a] == ELBM_BC_BOUNCEBACK;
   h->force = p->force[0] != 0.0 || p->force[1] != 0.0 || (h->D == 3 && p->force[2] != 0.0);
-  h->staged = use_staged(*p, h->wall);
+  h->staged = use_staged(*p);
   hipError_t e = hipGetDevice(&h->device);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&h->event, hipEventDisableTiming);
   if (e != hipSuccess) {

@@ -32,9 +32,10 @@
 //   step_kernel     -- register pull: a thread loads each of its node's Q
 //                      values with one buffer load (64 x 8 tiles, 512 threads;
 //                      D2Q9 strips of 256); every lattice class.
-//   step_kernel_lds -- LDS staged (16-bit storage, periodic D3Q27, full 64 x 16
-//                      tiles, 1024 threads): the block stages the rows its
-//                      tile pulls from with 16-byte loads and pulls from LDS.
+//   step_kernel_lds -- LDS staged (16-bit storage, D3Q27, full 64 x 16 tiles,
+//                      x and z periodic, y periodic or bounce-back; 1024
+//                      threads): the block stages the rows its tile pulls
+//                      from with 16-byte loads and pulls from LDS.
 // Both run the same per-node arithmetic (collide) on the same stored values.
 //
 // Arithmetic is FP32 on deviations h_i = f_i - w_i from the reference
@@ -52,6 +53,8 @@
 // run on one XCD at about the same time and their halo re-reads hit its L2.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
+
+#include <type_traits>
 
 #include "elbm_internal.h"
 
@@ -711,21 +714,22 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
 // ---------------------------------------------------------------------------
 // LDS-staged D3Q27 step for 16-bit storage.
 //
-// The kernel above issues one narrow load per pulled value; with 2-byte
-// elements that instruction stream, rather than HBM, sets its pace. Here a
-// block stages, for every direction i, the rows of plane z - c_iz that its
-// tile and halo nodes pull direction i from, in LDS: each row's 64 interior
-// nodes with 16-byte loads and the node pairs left and right of the tile with
-// 4-byte loads, three planes deep, so that the loads of plane z + 2 are in
-// flight while plane z is relaxed. A pull is then an LDS read at an offset
-// fixed per direction. It applies to periodic D3Q27 lattices whose n_x is a
-// multiple of 64 and n_y a multiple of 8 (full tiles); the others take the
-// kernel above.
+// The kernel above holds two of its three planes' populations in registers,
+// which caps it at two waves per SIMD; with 2-byte elements that occupancy,
+// rather than HBM, sets its pace. Here a block of 64 x TY nodes stages, for
+// every direction i, the rows of plane z - c_iz that its tile and halo nodes
+// pull direction i from, in LDS: each row's 64 interior nodes with 16-byte
+// loads and the node pairs left and right of the tile with 4-byte loads. The
+// stages of planes z (relaxation) and z + 1 (next anomaly) are resident (two
+// or three buffers), the loads of plane z + 2 fly in registers while plane z
+// is updated. A pull is then an LDS read at an offset fixed per direction. It
+// applies to D3Q27 lattices whose n_x is a multiple of 64 and n_y a multiple
+// of TY (full tiles), x and z periodic; the others take the kernel above.
 //
 // Staged row layout (bytes): [0, 128) the 64 interior nodes x0 ... x0 + 63,
 // [128, 132) the pair x0 - 2, x0 - 1, [132, 136) the pair x0 + 64, x0 + 65,
-// padding to 144. Direction i's box holds rows y0 - 1 - c_iy ... y0 + 8 - c_iy,
-// so a node of tile row ly reads row ly + 1 of every box.
+// padding to 144. Direction i's box holds rows y0 - 1 - c_iy ... y0 + TY -
+// c_iy, so a node of tile row ly reads row ly + 1 of every box.
 // ---------------------------------------------------------------------------
 namespace lds {
 constexpr int TX = 64, TY = kRowsStaged, NT = TX * TY;
@@ -752,7 +756,12 @@ __device__ __forceinline__ int col_byte(int dx) {
   return dx < 0 ? 128 + 2 * (dx + 2) : (dx < 64 ? 2 * dx : 132 + 2 * (dx - 64));
 }
 
-template <int S, bool FORCE>
+// WALLY: halfway bounce-back walls on y (x and z periodic). Rows beyond a wall
+// are staged like any other (their values go unused); a node of a row next to
+// a wall takes the populations that would arrive through it from its own
+// post-collision populations of the opposite directions, loaded directly, and
+// the anomaly beyond the wall is the odd ghost -Q~ of the wall row.
+template <int S, bool FORCE, bool WALLY>
 __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld, int64_t tl, int parity,
                                               unsigned char* __restrict__ smem) {
   using namespace lds;
@@ -762,7 +771,7 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
   constexpr int Q = 27;
 
   TileConst k;
-  load_const<false>(Ld, Q * sizeof(T), k);
+  load_const<WALLY>(Ld, Q * sizeof(T), k);
   const char* src = static_cast<const char*>(Ld->buf[parity]);
   const char* dst = static_cast<const char*>(Ld->buf[parity ^ 1]);
   const uint32_t sb0 = uint32_t(Ld->pstride) * 2u;
@@ -779,6 +788,12 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
   const int tid = threadIdx.x;
   const int lx = tid & 63, ly = tid >> 6;
   const int gx = x0 + lx, gy = y0 + ly;
+  // a wave is one tile row: wall rows are wave-uniform
+  const bool wall_lo = WALLY && k.w1 && y0 == 0, wall_hi = WALLY && k.w1 && y0 + TY == k.n1;
+  const int wrow = __builtin_amdgcn_readfirstlane(ly);
+  // +1: the populations with c_y = +1 arrive through the wall below, -1: those
+  // with c_y = -1 through the wall above, 0: no wall next to this row
+  const int wall_side = (wall_lo && wrow == 0) ? 1 : ((wall_hi && wrow == TY - 1) ? -1 : 0);
 
   float* anom = reinterpret_cast<float*>(smem + NSTAGE * STAGE);
   auto QX = [&](int b, int slot) -> float& { return anom[b * LXF + slot]; };
@@ -787,22 +802,29 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
   const int sx_own = ly * (TX + 2) + lx + 1, sxm = sx_own - 1, sxp = sx_own + 1;
   const int sy_own = (ly + 1) * TX + lx, sym = sy_own - TX, syp = sy_own + TX;
 
-  // halo node of this thread: tid < 128 the rows y0 - 1 and y0 + 8, then the
-  // columns x0 - 1 and x0 + 64 (tile-local coordinates hx, hy)
-  const bool has_halo = tid < 2 * TX + 2 * TY;
-  int hx = 0, hy = 0, hslot = 0, hax = 0;
+  // halo node of this thread: tid < 128 the rows y0 - 1 and y0 + TY, then the
+  // columns x0 - 1 and x0 + 64 (tile-local coordinates hx, hy); none beyond a
+  // wall
+  bool has_halo = tid < 2 * TX + 2 * TY;
+  int hx = 0, hy = 0, hslot = 0, hax = 0, h_side = 0;
   if (tid < 2 * TX) {
     const int side = tid >> 6;
     hx = lx;
     hy = side ? TY : -1;
     hslot = (side ? (TY + 1) * TX : 0) + lx;
     hax = 1;
+    if (side ? wall_hi : wall_lo) has_halo = false;
   } else if (has_halo) {
     const int q = tid - 2 * TX, side = q / TY, row = q % TY;
     hx = side ? TX : -1;
     hy = row;
     hslot = row * (TX + 2) + (side ? TX + 1 : 0);
+    h_side = (wall_lo && row == 0) ? 1 : ((wall_hi && row == TY - 1) ? -1 : 0);
   }
+  // in-plane byte offsets of the node and of its halo node (bounce-back loads)
+  const uint32_t own = uint32_t(gy * k.n0 + gx) * 2u;
+  const int hgx = x0 + hx < 0 ? x0 + hx + k.n0 : (x0 + hx >= k.n0 ? x0 + hx - k.n0 : x0 + hx);
+  const uint32_t hown = uint32_t((y0 + max(hy, 0)) * k.n0 + hgx) * 2u;
   const float h_uref = hax == 0 ? k.uref[0] : k.uref[1];
   const float h_anom = hax == 0 ? k.anom[0] : k.anom[1];
   const int hofs = hax == 0 ? 0 : 2 * LXF;  // the halo's axis: buffer 0, and the offset to buffer 1
@@ -819,17 +841,34 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
     const int c0 = cq<3>(i, 0);
     return *reinterpret_cast<const R*>(stg + i * BOX + base[c0 + 1]);
   };
-  // deviation moments of the values a node pulls from stage stg
-  auto moments = [&](const unsigned char* stg, const int (&base)[3], float& drho, float (&dj)[3]) {
+  // own post-collision population Q - 1 - i of plane p at in-plane offset off
+  auto bounce = [&](int p, uint32_t sb, uint32_t off, int i) -> R {
+    return Store<S>::load(rsrc(src + uint64_t(p) * k.slab_bytes), off, (Q - 1 - i) * sb);
+  };
+  // deviation moments of the values a node pulls from stage stg (plane p);
+  // side selects the directions taken by bounce-back (0: none)
+  auto moments_side = [&](auto side, const unsigned char* stg, const int (&base)[3], int p, uint32_t sb,
+                          uint32_t off, float& drho, float (&dj)[3]) {
+    constexpr int SIDE = decltype(side)::value;
     float v[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) v[i] = Store<S>::to_float(pull_lds(stg, base, i));
+    for (int i = 0; i < Q; ++i)
+      v[i] = Store<S>::to_float(SIDE != 0 && cq<3>(i, 1) == SIDE ? bounce(p, sb, off, i) : pull_lds(stg, base, i));
     float r, m[3];
     Puller<3, S, false>::line_moments(v, r, m);
     drho = r * k.inv_scale;
     dj[0] = k.mfac[0] * m[0];
     dj[1] = k.mfac[1] * m[1];
     dj[2] = k.mfac[2] * m[2];
+  };
+  using Side0 = std::integral_constant<int, 0>;
+  using SideLo = std::integral_constant<int, 1>;
+  using SideHi = std::integral_constant<int, -1>;
+  auto node_moments = [&](int side, const unsigned char* stg, const int (&base)[3], int p, uint32_t sb,
+                          uint32_t off, float& dr, float (&djo)[3]) {
+    if (WALLY && side == 1) moments_side(SideLo(), stg, base, p, sb, off, dr, djo);
+    else if (WALLY && side == -1) moments_side(SideHi(), stg, base, p, sb, off, dr, djo);
+    else moments_side(Side0(), stg, base, p, sb, off, dr, djo);
   };
 
   // ---- staging: this thread's loads (fixed along the march) ----
@@ -890,15 +929,16 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
 
   // next-plane anomaly of the node (ring) and of its halo node, from stage stg
   float drho, dj[3], qc[3] = {0.f, 0.f, 0.f}, qprev;
-  auto plane_anomalies = [&](const unsigned char* stg, int bo, float& dr, float (&djo)[3], float (&q)[3]) {
-    moments(stg, rb, dr, djo);
+  auto plane_anomalies = [&](const unsigned char* stg, int p, uint32_t sb, int bo, float& dr, float (&djo)[3],
+                             float (&q)[3]) {
+    node_moments(wall_side, stg, rb, p, sb, own, dr, djo);
     const float ir = recip(1.f + dr);
     q[0] = anomaly(k, 0, djo[0], ir);
     q[1] = anomaly(k, 1, djo[1], ir);
     q[2] = anomaly(k, 2, djo[2], ir);
     if (has_halo) {
       float hr, hj[3];
-      moments(stg, hb, hr, hj);
+      node_moments(h_side, stg, hb, p, sb, hown, hr, hj);
       const float j = h_uref + (hax == 0 ? hj[0] : hj[1]);
       const float u = j * recip(1.f + hr);
       anom[hofs + bo * hstep + hslot] = j * h_anom - j * u * u;
@@ -919,9 +959,9 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
     stage_store(smem + STAGE, g);
     __syncthreads();
     float dr, djp[3];
-    moments(smem, rb, dr, djp);
+    node_moments(wall_side, smem, rb, plane_index(z0 - 1), sb0, own, dr, djp);
     qprev = anomaly(k, 2, djp[2], recip(1.f + dr));
-    plane_anomalies(smem + STAGE, 0, drho, dj, qc);
+    plane_anomalies(smem + STAGE, z0, sb0, 0, drho, dj, qc);
     QX(0, sx_own) = qc[0];
     QY(0, sy_own) = qc[1];
     if (NSTAGE == 3) {
@@ -949,18 +989,28 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
 
     // next plane: own anomaly (closes the ring) and the halo's
     float drn, djn[3], qn[3];
-    plane_anomalies(smem + bz1 * STAGE, b ^ 1, drn, djn, qn);
+    plane_anomalies(smem + bz1 * STAGE, plane_index(z + 1), sb, b ^ 1, drn, djn, qn);
 
     // collision of plane z
     {
       float Gd[3];
       Gd[0] = (QX(b, sxp) - QX(b, sxm)) * k.hil[0];
-      Gd[1] = (QY(b, syp) - QY(b, sym)) * k.hil[1];
+      // beyond a wall the anomaly is the odd ghost of the wall row
+      const float qym = wall_side == 1 ? -qc[1] : QY(b, sym);
+      const float qyp = wall_side == -1 ? -qc[1] : QY(b, syp);
+      Gd[1] = (qyp - qym) * k.hil[1];
       Gd[2] = (qn[2] - qprev) * k.hil[2];
       const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
-      const uint32_t own = uint32_t(gy * k.n0 + gx) * 2u;
-      collide<3, FORCE>(k, drho, dj, Gd, [&](int i) { return Store<S>::to_float(pull_lds(s_z, rb, i)); },
-                        [&](int i, float o) { Store<S>::store(rd, own, i * sb, o); });
+      auto emit = [&](int i, float o) { Store<S>::store(rd, own, i * sb, o); };
+      auto pulled = [&](auto side) {
+        constexpr int SIDE = decltype(side)::value;
+        return [&, z, sb](int i) {
+          return Store<S>::to_float(SIDE != 0 && cq<3>(i, 1) == SIDE ? bounce(z, sb, own, i) : pull_lds(s_z, rb, i));
+        };
+      };
+      if (WALLY && wall_side == 1) collide<3, FORCE>(k, drho, dj, Gd, pulled(SideLo()), emit);
+      else if (WALLY && wall_side == -1) collide<3, FORCE>(k, drho, dj, Gd, pulled(SideHi()), emit);
+      else collide<3, FORCE>(k, drho, dj, Gd, pulled(Side0()), emit);
     }
     QX(b ^ 1, sx_own) = qn[0];
     QY(b ^ 1, sy_own) = qn[1];
@@ -992,7 +1042,7 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
   }
 }
 
-template <int S, bool FORCE>
+template <int S, bool FORCE, bool WALLY>
 __global__ void __launch_bounds__(lds::NT)
     step_kernel_lds(const TableHeader* __restrict__ hdr, const LatticeDesc* __restrict__ table, int64_t substep) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[lds::BYTES];
@@ -1010,7 +1060,7 @@ __global__ void __launch_bounds__(lds::NT)
     const LatticeDesc* d = table + L;
     if (substep < d->nsteps) {
       const int parity = (d->parity0 + int(substep & 1)) & 1;
-      step_tile_lds<S, FORCE>(d, t - d->tile_base, parity, smem);
+      step_tile_lds<S, FORCE, WALLY>(d, t - d->tile_base, parity, smem);
     }
     __syncthreads();
   }
@@ -1059,10 +1109,19 @@ hipError_t launch_ds(bool wall, bool force, const TableHeader* hdr, const Lattic
                : launch_one<D, S, false, false>(hdr, table, s, grid, st);
 }
 
-template <int S, bool FORCE>
+template <int S, bool FORCE, bool WALLY>
 hipError_t launch_lds(const TableHeader* hdr, const LatticeDesc* table, int64_t substep, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((step_kernel_lds<S, FORCE>), dim3(grid), dim3(lds::NT), 0, st, hdr, table, substep);
+  hipLaunchKernelGGL((step_kernel_lds<S, FORCE, WALLY>), dim3(grid), dim3(lds::NT), 0, st, hdr, table, substep);
   return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_lds_s(bool wall, bool force, const TableHeader* hdr, const LatticeDesc* table, int64_t s,
+                        int grid, hipStream_t st) {
+  if (wall) return force ? launch_lds<S, true, true>(hdr, table, s, grid, st)
+                         : launch_lds<S, false, true>(hdr, table, s, grid, st);
+  return force ? launch_lds<S, true, false>(hdr, table, s, grid, st)
+               : launch_lds<S, false, false>(hdr, table, s, grid, st);
 }
 
 }  // namespace
@@ -1078,11 +1137,18 @@ int occupancy_one() {
   return n > 0 ? n : 1;
 }
 
-template <int S, bool FORCE>
+template <int S, bool FORCE, bool WALLY>
 int occupancy_lds() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_lds<S, FORCE>, lds::NT, 0) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_lds<S, FORCE, WALLY>, lds::NT, 0) != hipSuccess)
+    return 1;
   return n > 0 ? n : 1;
+}
+
+template <int S>
+int occupancy_lds_s(bool wall, bool force) {
+  if (wall) return force ? occupancy_lds<S, true, true>() : occupancy_lds<S, false, true>();
+  return force ? occupancy_lds<S, true, false>() : occupancy_lds<S, false, false>();
 }
 
 template <int D, int S>
@@ -1092,10 +1158,8 @@ int occupancy_ds(bool wall, bool force) {
 }
 
 int step_blocks_per_cu(int D, int storage, bool wall, bool force, bool staged) {
-  if (staged && D == 3 && !wall && storage != 0) {
-    if (storage == 1) return force ? occupancy_lds<1, true>() : occupancy_lds<1, false>();
-    return force ? occupancy_lds<2, true>() : occupancy_lds<2, false>();
-  }
+  if (staged && D == 3 && storage != 0) return storage == 1 ? occupancy_lds_s<1>(wall, force)
+                                                             : occupancy_lds_s<2>(wall, force);
   if (D == 3) {
     switch (storage) {
       case 0: return occupancy_ds<3, 0>(wall, force);
@@ -1114,11 +1178,10 @@ hipError_t launch_step(int D, int storage, bool wall, bool force, bool staged, c
                        const LatticeDesc* table, int64_t substep, int grid, hipStream_t st) {
   if (grid <= 0 || (grid & 7)) return hipErrorInvalidConfiguration;
   if (staged) {
-    if (D != 3 || wall || (storage != 1 && storage != 2)) return hipErrorInvalidValue;
-    if (storage == 1) return force ? launch_lds<1, true>(hdr, table, substep, grid, st)
-                                   : launch_lds<1, false>(hdr, table, substep, grid, st);
-    return force ? launch_lds<2, true>(hdr, table, substep, grid, st)
-                 : launch_lds<2, false>(hdr, table, substep, grid, st);
+    // (wall: bounce-back on y only; the host admits no other walls here)
+    if (D != 3 || (storage != 1 && storage != 2)) return hipErrorInvalidValue;
+    return storage == 1 ? launch_lds_s<1>(wall, force, hdr, table, substep, grid, st)
+                        : launch_lds_s<2>(wall, force, hdr, table, substep, grid, st);
   }
   if (D == 3) {
     switch (storage) {
