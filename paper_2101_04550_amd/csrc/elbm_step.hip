@@ -422,21 +422,33 @@ __device__ __forceinline__ void collide(const TileConst& k, float drho, const fl
         A[c0][c1] = drs * p[0][c0] + ds[0][c0];
       }
     }
+  // Force F_i = rho (prod (pe + e) - prod pe) in storage scale, with the
+  // factor scale rho folded into the x-axis triplets once per node:
+  // F_i scale = dY (pe_z + e_z) + Y e_z, Y = sx_x pe_y, dY = ex_x (pe_y + e_y) + sx_x e_y,
+  // sx = scale rho pe_x, ex = scale rho e_x (D2Q9: pe_y = 1, e_y = 0).
+  float sx[3], ex[3], qz[3];
+  if (FORCE) {
+    const float sr = k.scale * rho;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sx[c] = sr * pe[0][c];
+      ex[c] = sr * e[0][c];
+      qz[c] = pe[2][c] + e[2][c];
+    }
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int c0 = cq<D>(i, 0) + 1, c1 = cq<D>(i, 1) + 1, c2 = cq<D>(i, 2) + 1;
     const float Wc = D == 3 ? k.WW[c0][c1] : k.W[0][c0];
     float o = A[c0][c1] * p[2][c2] + Wc * ds[2][c2];
     if (FORCE) {
-      float fr;
       if (D == 3) {
-        const float Y = pe[0][c0] * pe[1][c1];
-        const float dY = e[0][c0] * (pe[1][c1] + e[1][c1]) + pe[0][c0] * e[1][c1];
-        fr = rho * (dY * (pe[2][c2] + e[2][c2]) + Y * e[2][c2]);
+        const float Y = sx[c0] * pe[1][c1];
+        const float dY = ex[c0] * (pe[1][c1] + e[1][c1]) + sx[c0] * e[1][c1];
+        o += dY * qz[c2] + Y * e[2][c2];
       } else {
-        fr = rho * (e[0][c0] * (pe[2][c2] + e[2][c2]) + pe[0][c0] * e[2][c2]);
+        o += ex[c0] * qz[c2] + sx[c0] * e[2][c2];
       }
-      o += k.scale * fr;
     }
     emit(i, k.om1 * hval(i) + o);
   }
