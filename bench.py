@@ -34,6 +34,15 @@ N_HIT = 256
 OMEGA_HIT = 1.892885
 T_HIT = 0.5
 DIAG_EVERY = 50
+# Channel workload (Sec. 3.5 at Re_tau = 180): 384 x 192 x 192 on the lattice
+# stretched to lambda = (2, 1, 1), half-width H = 96 rows, T = 0.5; omega from
+# the friction-velocity estimate, the force g = Re_tau^2 nu^2 / H^3.
+CHANNEL_N = (384, 192, 192)
+CHANNEL_LAM = (2.0, 1.0, 1.0)
+CHANNEL_H = 96
+CHANNEL_RE_TAU = 180.0
+CHANNEL_T = 0.5
+CHANNEL_OMEGA = 1.976785
 PMC_FILE = os.path.join(ROOT, "profiles", "step_d3q27_f32_hit256_pmc.txt")
 STEP_SOURCE = os.path.join(ROOT, "paper_2101_04550_amd", "csrc", "elbm_step.hip")
 
@@ -211,6 +220,13 @@ def d2q9_leg(n=1024, steps=2000):
     return out
 
 
+def channel_force():
+    """Body force of the channel workload, g = Re_tau^2 nu^2 / H^3 (Sec. 3.5),
+    with nu = (1/omega - 1/2) T (Sec. 2.1, eq. nu)."""
+    nu = (1 / CHANNEL_OMEGA - 0.5) * CHANNEL_T
+    return CHANNEL_RE_TAU ** 2 * nu ** 2 / CHANNEL_H ** 3
+
+
 def channel_leg(steps=300):
     """D3Q27 channel on the stretched lattice (dy/dx = 0.5): 384 x 192 x 192,
     bounce-back walls in y, body force for Re_tau = 180, T = 0.5,
@@ -221,14 +237,13 @@ def channel_leg(steps=300):
     import inputs as I
     from paper_2101_04550_amd import elbm as E
 
-    n, lam, omega = (384, 192, 192), (2.0, 1.0, 1.0), 1.976785
-    nu = (1 / omega - 0.5) * 0.5
-    g = 180.0 ** 2 * nu ** 2 / 96.0 ** 3
+    n, lam, omega = CHANNEL_N, CHANNEL_LAM, CHANNEL_OMEGA
+    g = channel_force()
     fld = I.channel_field(n, lam)
     N = math.prod(n)
     out = {}
     for st in ("f32", "f16"):
-        lat = E.Lattice(E.make_params(n, lam=lam, T=0.5, omega=omega, walls=(False, True, False),
+        lat = E.Lattice(E.make_params(n, lam=lam, T=CHANNEL_T, omega=omega, walls=(False, True, False),
                                       force=(g, 0.0, 0.0), storage=st))
         lat.init(fld.rho, fld.u)
         info = lat.kernel_info()

@@ -31,19 +31,6 @@ def test_velocity_set_and_opposite(D):
     np.testing.assert_array_equal(O.opposite(c), Q - 1 - np.arange(Q))
 
 
-@pytest.mark.parametrize("D,expected", [
-    (2, {0: 4 / 9, 1: 1 / 9, 2: 1 / 36}),
-    (3, {0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216}),
-])
-def test_textbook_weights(D, expected):
-    """lam = 1 and T = T_L = 1/3 (Sec. 2.3, eq. TL) give the textbook D2Q9 / D3Q27
-    weights at rest, keyed by the number of non-zero velocity components."""
-    p = O.Params(n=(1,) * D, T=1.0 / 3.0)
-    w = O.equilibrium(np.array(1.0), np.zeros(D), p.T, p.lam, p.c)
-    for i, ci in enumerate(p.c):
-        assert abs(w[i] - expected[int(np.abs(ci).sum())]) < 1e-15
-
-
 @pytest.mark.parametrize("D", [2, 3])
 def test_second_order_truncation_is_polynomial_equilibrium(D):
     """At lam = 1, T = 1/3 the product-form equilibrium equals the textbook
