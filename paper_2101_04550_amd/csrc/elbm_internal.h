@@ -33,13 +33,9 @@ namespace elbm {
 #ifndef ELBM_TYS
 #define ELBM_TYS 16
 #endif
-#ifndef ELBM_NSTAGE
-#define ELBM_NSTAGE 2
-#endif
 constexpr int kTileX3 = ELBM_TX3;  // x width of a D3Q27 tile
 constexpr int kRows3 = ELBM_TY3;   // y rows of a D3Q27 tile
 constexpr int kRowsStaged = ELBM_TYS;     // y rows of a tile of the LDS-staged kernel (x width 64)
-constexpr int kStagesStaged = ELBM_NSTAGE;  // planes the LDS-staged kernel holds in LDS (2 or 3)
 constexpr int kStrips2 = 4;        // 64-wide strips of a D2Q9 tile -> 256 threads
 constexpr int kDiagBlocks = 1024;  // fixed grid of the diagnostic reductions
 constexpr int kRec = 16;           // doubles per diagnostic record / partial

@@ -120,6 +120,11 @@ struct Store<2> {
 __device__ __forceinline__ void drain_vm() { __builtin_amdgcn_s_waitcnt(0xF70); }
 // ... and its LDS / scalar-memory operations as well.
 __device__ __forceinline__ void drain_all() { __builtin_amdgcn_s_waitcnt(0); }
+// Waits until at most 27 vector-memory operations of this wave are in flight:
+// the counter retires in issue order, so after the 27 stores of a D3Q27 node
+// every earlier load is complete while the stores may still be in flight
+// (vmcnt(27): low bits 0xB, high bits 0x4000; expcnt and lgkmcnt open).
+__device__ __forceinline__ void wait_vm_but_stores() { __builtin_amdgcn_s_waitcnt(0x4F7B); }
 
 // 1/x with the hardware reciprocal (1 ulp).
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -475,6 +480,13 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   const int x0 = t0 * TXW, y0 = t1 * TYR;
   const int z0 = t2 * chunk;
   const int z1 = min(z0 + chunk, k.n2);
+  // Odd chunks march down the axis: the ring planes at the face between two
+  // chunks are then read by both tiles at about the same time (both early or
+  // both late in the step), so the second read is a cache hit instead of an
+  // HBM read. Reversing the march changes no result: the z difference takes
+  // the sign of the march, and every operation is otherwise the same.
+  const int dir = (t2 & 1) ? -1 : 1;
+  const int zs = dir > 0 ? z0 : z1 - 1, len = z1 - z0;
   const int xe = min(x0 + TXW, k.n0), ye = min(y0 + TYR, k.n1);
 
   const int tid = threadIdx.x;
@@ -595,8 +607,8 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   const uint32_t sb0 = uint32_t(Ld->pstride) * uint32_t(sizeof(T));
 
   // Populations in flight: while plane z is relaxed one set holds plane z,
-  // one plane z + 1 (fetched a plane ahead) and one receives plane z + 2; hp
-  // holds the halo node's next plane.
+  // one the next plane in march order (fetched a plane ahead) and one receives
+  // the plane after it; hp holds the halo node's next plane.
   Pops<S, Q> P0, P1, P2, hp;
   float drho = 0.f, dj[3] = {0.f, 0.f, 0.f};
   float qc[3] = {0.f, 0.f, 0.f};  // anomaly of the current plane at this node
@@ -605,7 +617,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   // fetches of the second ----
   {
     bool ghost_prev;
-    const int zp = plane(z0 - 1, ghost_prev);
+    const int zp = plane(zs - dir, ghost_prev);
     {
       float dr, djp[3];
       const PlaneSrc sp = src_planes(zp);
@@ -613,7 +625,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       P::moments(k, P2, dr, djp);
       qprev = anomaly(k, 2, djp[2], recip(1.f + dr));
     }
-    const PlaneSrc s0 = src_planes(z0);
+    const PlaneSrc s0 = src_planes(zs);
     P::fetch(sb0, s0, no, near(s0), P0);
     P::moments(k, P0, drho, dj);
     {
@@ -628,7 +640,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       }
     }
     bool ghost1;
-    const PlaneSrc s1 = src_planes(plane(z0 + 1, ghost1));
+    const PlaneSrc s1 = src_planes(plane(zs + dir, ghost1));
     P::fetch(sb0, s1, no, near(s1), P1);
     if (has_halo) {
       P::fetch(sb0, s0, hno, near(s0), hp);
@@ -641,17 +653,19 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
   // One plane of the march. The three population sets rotate roles from
   // plane to plane (the loop below is unrolled by three), so that no register
   // receiving a fetch is ever copied before its load has landed.
-  auto march = [&](int z, const Pops<S, Q>& h, const Pops<S, Q>& pf1, Pops<S, Q>& pf2) {
-    const int b = (z - z0) & 1;
+  const float hz = dir > 0 ? k.hil[2] : -k.hil[2];  // z difference in march order
+  auto march = [&](int m, const Pops<S, Q>& h, const Pops<S, Q>& pf1, Pops<S, Q>& pf2) {
+    const int z = zs + dir * m;
+    const int b = m & 1;
     // The array distance is made opaque per plane so that the per-direction
     // offsets are formed in scalar registers where they are used rather than
     // held across the march.
     uint32_t sb = sb0;
     asm("" : "+s"(sb) : "s"(z));
-    const bool more = z + 1 < z1;
+    const bool more = m + 1 < len;
     bool ghost_next, ghost2;
-    plane(z + 1, ghost_next);
-    const PlaneSrc s2 = src_planes(plane(z + 2, ghost2));
+    plane(z + dir, ghost_next);
+    const PlaneSrc s2 = src_planes(plane(z + 2 * dir, ghost2));
     // The fetches and the moments below are issued on every plane and by every
     // lane (lanes beyond a ragged edge work on a clamped node; at the end of a
     // chunk or behind a wall the fetched plane goes unused), so that the code
@@ -674,7 +688,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     // than the algorithmic bytes at 256^3 FP32, against 6% with the drains,
     // and 6% longer steps).
     drain_vm();
-    // halo of plane z + 1 (fetched one plane ahead), then the fetch of z + 2
+    // halo of the next plane (fetched one plane ahead), then the fetch two planes on
     if (has_halo) {
       halo_store(hp, b ^ 1);
       P::fetch(sb, s2, hno, near(s2), hp);
@@ -694,7 +708,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
         const float qyp = gyp ? -qc[1] : QY(b, syp);
         Gd[1] = (qyp - qym) * k.hil[1];
       }
-      Gd[2] = (qnext - qprev) * k.hil[2];
+      Gd[2] = (qnext - qprev) * hz;
 
       const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
       collide<D, FORCE>(k, drho, dj, Gd, [&](int i) { return h.get(i); },
@@ -716,10 +730,10 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     qc[1] = qn[1];
     qc[2] = qnext;
   };
-  for (int z = z0; z < z1; z += 3) {
-    march(z, P0, P1, P2);
-    if (z + 1 < z1) march(z + 1, P1, P2, P0);
-    if (z + 2 < z1) march(z + 2, P2, P0, P1);
+  for (int m = 0; m < len; m += 3) {
+    march(m, P0, P1, P2);
+    if (m + 1 < len) march(m + 1, P1, P2, P0);
+    if (m + 2 < len) march(m + 2, P2, P0, P1);
   }
 }
 
@@ -730,43 +744,62 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
 // which caps it at two waves per SIMD; with 2-byte elements that occupancy,
 // rather than HBM, sets its pace. Here a block of 64 x TY nodes stages, for
 // every direction i, the rows of plane z - c_iz that its tile and halo nodes
-// pull direction i from, in LDS: each row's 64 interior nodes with 16-byte
-// loads and the node pairs left and right of the tile with 4-byte loads. The
-// stages of planes z (relaxation) and z + 1 (next anomaly) are resident (two
-// or three buffers), the loads of plane z + 2 fly in registers while plane z
-// is updated. A pull is then an LDS read at an offset fixed per direction. It
-// applies to D3Q27 lattices whose n_x is a multiple of 64 and n_y a multiple
-// of TY (full tiles), x and z periodic; the others take the kernel above.
+// pull direction i from, in LDS, with direct buffer-to-LDS loads (no
+// registers in between): a row's 64 interior nodes in 16-byte pieces, and the
+// node pairs left and right of the tile in 4-byte pieces. A pull is then an
+// LDS read at an offset fixed per direction. Two planes are staged: the next
+// plane in march order, whose values give its anomaly (and are kept in
+// registers, two per register, for its relaxation one plane later), and the
+// plane after it, whose loads fly while the current plane is relaxed. One
+// barrier per plane separates a stage's reads from its reloading.
+// It applies to D3Q27 lattices whose n_x is a multiple of 64 and n_y a
+// multiple of TY (full tiles), x and z periodic; the others take the kernel
+// above.
 //
-// Staged row layout (bytes): [0, 128) the 64 interior nodes x0 ... x0 + 63,
-// [128, 132) the pair x0 - 2, x0 - 1, [132, 136) the pair x0 + 64, x0 + 65,
-// padding to 144. Direction i's box holds rows y0 - 1 - c_iy ... y0 + TY -
-// c_iy, so a node of tile row ly reads row ly + 1 of every box.
+// Stage layout (bytes): 27 boxes of BOX bytes, direction i's at i BOX. Box
+// row r (0 ... TY + 1) holds lattice row y0 - 1 - c_iy + r, so a node of tile
+// row ly reads row ly + 1 of every box: the 64 interior nodes x0 ... x0 + 63
+// at r 128, and, after the TY + 2 interior rows, the pairs x0 - 2, x0 - 1
+// and x0 + 64, x0 + 65 of each row at SIDE + 8 r and SIDE + 8 r + 4. A direct
+// load writes 16 (or 4) bytes per lane to consecutive LDS addresses from a
+// per-instruction base, so each box is written by three instructions of
+// 16-byte pieces (eight rows each) and one of 4-byte side pieces.
 // ---------------------------------------------------------------------------
 namespace lds {
-constexpr int TX = 64, TY = kRowsStaged, NT = TX * TY;
-constexpr int ROWB = 144;
-constexpr int BOX = (TY + 2) * ROWB;
+constexpr int TX = 64, TY = kRowsStaged, NT = TX * TY, NW = NT / 64;
+constexpr int ROWS = TY + 2;                    // box rows
+constexpr int SIDE = ROWS * 128;                // side pairs of a box
+constexpr int BOX = SIDE + ROWS * 8;
 constexpr int STAGE = 27 * BOX;
-constexpr int NSTAGE = kStagesStaged;
-constexpr int LXF = TY * (TX + 2);  // anomaly exchange, axis 0 (floats per buffer)
-constexpr int LYF = (TY + 2) * TX;  // anomaly exchange, axis 1
-constexpr int BYTES = NSTAGE * STAGE + 2 * (LXF + LYF) * 4;
-constexpr int CHUNKS = 9 * (TY + 2) * 8;  // 16-byte interior loads per c_z group
-constexpr int PAIRS = 9 * (TY + 2) * 2;   // 4-byte side-pair loads per c_z group
-static_assert(CHUNKS <= 2 * NT && PAIRS <= NT, "staging covers a group in two passes");
-static_assert(STAGE % 16 == 0 && BOX % 16 == 0 && ROWB % 16 == 0, "16-byte LDS stores stay aligned");
-static_assert(NSTAGE == 2 || NSTAGE == 3, "two or three staged planes");
+constexpr int LXF = TY * (TX + 2);              // anomaly exchange, axis 0 (floats per buffer)
+constexpr int LYF = (TY + 2) * TX;              // anomaly exchange, axis 1
+constexpr int BYTES = 2 * STAGE + 2 * (LXF + LYF) * 4;
+constexpr int IITEMS = ROWS * 8;                // 16-byte pieces of a box
+constexpr int IINSTR = (IITEMS + 63) / 64;      // wave instructions for them
+constexpr int SITEMS = ROWS * 2;                // 4-byte side pieces of a box
+constexpr int PER_BOX = IINSTR + 1;            // wave instructions per box
+static_assert(SITEMS <= 64, "one wave instruction stages the side pairs of a box");
+static_assert(BOX % 16 == 0 && STAGE % 16 == 0, "16-byte aligned stage destinations");
 static_assert(BYTES <= 160 * 1024, "LDS of one block");
-static_assert(NT <= 1024 && TY % 2 == 0, "one block per tile");
+static_assert(NT <= 1024 && NT % 64 == 0 && TY % 2 == 0, "one block per tile");
 }  // namespace lds
 
-using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+using lds_ptr = __attribute__((address_space(3))) unsigned char*;
 
-// Byte of staged column dx = x - x0 (dx in [-2, 65]) within a row.
-__device__ __forceinline__ int col_byte(int dx) {
-  return dx < 0 ? 128 + 2 * (dx + 2) : (dx < 64 ? 2 * dx : 132 + 2 * (dx - 64));
+// Byte of staged column dx = x - x0 (dx in [-2, 65]) of box row r.
+__device__ __forceinline__ int col_byte(int dx, int r) {
+  using namespace lds;
+  return dx < 0 ? SIDE + 8 * r + 2 * (dx + 2) : (dx < 64 ? 128 * r + 2 * dx : SIDE + 8 * r + 4 + 2 * (dx - 64));
 }
+
+// The 27 values of a node, two 16-bit values per register (value i in half
+// i & 1 of word i / 2).
+struct Held {
+  uint32_t w[14];
+  __device__ __forceinline__ unsigned short get(int i) const {
+    return (i & 1) ? static_cast<unsigned short>(w[i >> 1] >> 16) : static_cast<unsigned short>(w[i >> 1]);
+  }
+};
 
 // WALLY: halfway bounce-back walls on y (x and z periodic). Rows beyond a wall
 // are staged like any other (their values go unused); a node of a row next to
@@ -796,18 +829,21 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
   const int x0 = t0 * TX, y0 = t1 * TY;
   const int z0 = t2 * chunk;
   const int z1 = min(z0 + chunk, k.n2);
+  // odd chunks march down the axis (see the kernel above)
+  const int dir = (t2 & 1) ? -1 : 1;
+  const int zs = dir > 0 ? z0 : z1 - 1, len = z1 - z0;
 
   const int tid = threadIdx.x;
   const int lx = tid & 63, ly = tid >> 6;
   const int gx = x0 + lx, gy = y0 + ly;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // a wave is one tile row: wall rows are wave-uniform
   const bool wall_lo = WALLY && k.w1 && y0 == 0, wall_hi = WALLY && k.w1 && y0 + TY == k.n1;
-  const int wrow = __builtin_amdgcn_readfirstlane(ly);
   // +1: the populations with c_y = +1 arrive through the wall below, -1: those
   // with c_y = -1 through the wall above, 0: no wall next to this row
-  const int wall_side = (wall_lo && wrow == 0) ? 1 : ((wall_hi && wrow == TY - 1) ? -1 : 0);
+  const int wall_side = (wall_lo && wave == 0) ? 1 : ((wall_hi && wave == TY - 1) ? -1 : 0);
 
-  float* anom = reinterpret_cast<float*>(smem + NSTAGE * STAGE);
+  float* anom = reinterpret_cast<float*>(smem + 2 * STAGE);
   auto QX = [&](int b, int slot) -> float& { return anom[b * LXF + slot]; };
   auto QY = [&](int b, int slot) -> float& { return anom[2 * LXF + b * LYF + slot]; };
   // anomaly slots of the node and of its tiled-axis neighbours (periodic, full tiles)
@@ -846,8 +882,8 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
   int rb[3], hb[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    rb[c] = (ly + 1) * ROWB + col_byte(lx - (c - 1));
-    hb[c] = (hy + 1) * ROWB + col_byte(hx - (c - 1));
+    rb[c] = col_byte(lx - (c - 1), ly + 1);
+    hb[c] = col_byte(hx - (c - 1), hy + 1);
   }
   auto pull_lds = [&](const unsigned char* stg, const int (&base)[3], int i) -> R {
     const int c0 = cq<3>(i, 0);
@@ -857,100 +893,111 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
   auto bounce = [&](int p, uint32_t sb, uint32_t off, int i) -> R {
     return Store<S>::load(rsrc(src + uint64_t(p) * k.slab_bytes), off, (Q - 1 - i) * sb);
   };
-  // deviation moments of the values a node pulls from stage stg (plane p);
-  // side selects the directions taken by bounce-back (0: none)
-  auto moments_side = [&](auto side, const unsigned char* stg, const int (&base)[3], int p, uint32_t sb,
-                          uint32_t off, float& drho, float (&dj)[3]) {
-    constexpr int SIDE = decltype(side)::value;
-    float v[Q];
+  // the values a node pulls from stage stg (plane p); side selects the
+  // directions taken by bounce-back (0: none)
+  auto values_side = [&](auto side, const unsigned char* stg, const int (&base)[3], int p, uint32_t sb,
+                         uint32_t off, R (&v)[Q]) {
+    constexpr int SIDE_ = decltype(side)::value;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      v[i] = Store<S>::to_float(SIDE != 0 && cq<3>(i, 1) == SIDE ? bounce(p, sb, off, i) : pull_lds(stg, base, i));
-    float r, m[3];
-    Puller<3, S, false>::line_moments(v, r, m);
-    drho = r * k.inv_scale;
-    dj[0] = k.mfac[0] * m[0];
-    dj[1] = k.mfac[1] * m[1];
-    dj[2] = k.mfac[2] * m[2];
+      v[i] = SIDE_ != 0 && cq<3>(i, 1) == SIDE_ ? bounce(p, sb, off, i) : pull_lds(stg, base, i);
   };
   using Side0 = std::integral_constant<int, 0>;
   using SideLo = std::integral_constant<int, 1>;
   using SideHi = std::integral_constant<int, -1>;
-  auto node_moments = [&](int side, const unsigned char* stg, const int (&base)[3], int p, uint32_t sb,
-                          uint32_t off, float& dr, float (&djo)[3]) {
-    if (WALLY && side == 1) moments_side(SideLo(), stg, base, p, sb, off, dr, djo);
-    else if (WALLY && side == -1) moments_side(SideHi(), stg, base, p, sb, off, dr, djo);
-    else moments_side(Side0(), stg, base, p, sb, off, dr, djo);
+  auto node_values = [&](int side, const unsigned char* stg, const int (&base)[3], int p, uint32_t sb,
+                         uint32_t off, R (&v)[Q]) {
+    if (WALLY && side == 1) values_side(SideLo(), stg, base, p, sb, off, v);
+    else if (WALLY && side == -1) values_side(SideHi(), stg, base, p, sb, off, v);
+    else values_side(Side0(), stg, base, p, sb, off, v);
+  };
+  // deviation moments of pulled values
+  auto moments = [&](const R (&v)[Q], float& dr, float (&djo)[3]) {
+    float f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = Store<S>::to_float(v[i]);
+    float r, m[3];
+    Puller<3, S, false>::line_moments(f, r, m);
+    dr = r * k.inv_scale;
+    djo[0] = k.mfac[0] * m[0];
+    djo[1] = k.mfac[1] * m[1];
+    djo[2] = k.mfac[2] * m[2];
   };
 
-  // ---- staging: this thread's loads (fixed along the march) ----
-  // Interior chunks a and b and one side pair, per c_z group; group g covers
-  // directions 9 g ... 9 g + 8, i.e. array j of the group is direction 9 g + j,
-  // so group g adds 9 g arrays to both offsets. Chunk b and the pair are
-  // issued only by the waves that hold such items (a wave-uniform test);
-  // within the last of those waves the spare lanes repeat the final item.
-  static_assert(CHUNKS >= NT, "every thread stages an interior chunk a");
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const bool wave_b = wave * 64 < CHUNKS - NT, wave_p = wave * 64 < PAIRS;
-  uint32_t voff[3];
-  int loff[3];
-  {
-    const int items[2] = {tid, min(tid + NT, CHUNKS - 1)};
+  // ---- staging: this wave's direct loads (fixed along the march) ----
+  // The stage's wave instructions are taken in rounds of NW: in round t, wave
+  // w writes piece kind w % PER_BOX (interior instructions, then the side
+  // pairs) of box j = (NW / PER_BOX) t + w / PER_BOX, so a wave's kind, and which of
+  // its lanes hold a piece, are fixed. dv is this lane's byte offset within a
+  // plane slab for box j (direction j's array and the row and column the
+  // piece comes from); the source plane p - c_jz enters through the buffer
+  // resource.
+  static_assert(NW % PER_BOX == 0, "a wave keeps its piece kind from round to round");
+  constexpr int BPR = NW / PER_BOX;  // boxes per round
+  constexpr int ROUNDS = (27 + BPR - 1) / BPR;
+  const int kind = wave % PER_BOX, jw = wave / PER_BOX;
+  const bool side_kind = kind == IINSTR;
+  const bool dok = side_kind ? lx < SITEMS : 64 * kind + lx < IITEMS;
+  uint32_t dv[ROUNDS];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int it = items[u];
-      const int j = it / ((TY + 2) * 8), r = (it >> 3) % (TY + 2), q = it & 7;
-      const int c1 = j / 3 - 1;
-      int ys = y0 - 1 - c1 + r;
-      ys = ys < 0 ? ys + k.n1 : (ys >= k.n1 ? ys - k.n1 : ys);
-      voff[u] = j * sb0 + uint32_t(ys * k.n0 + x0) * 2u + 16u * q;
-      loff[u] = j * BOX + r * ROWB + 16 * q;
+  for (int t = 0; t < ROUNDS; ++t) {
+    const int j = min(BPR * t + jw, 26);
+    const int c1 = cq<3>(j, 1);
+    if (!side_kind) {
+      const int it = 64 * kind + lx;
+      const int r = min(it >> 3, ROWS - 1), q = it & 7;
+      dv[t] = uint32_t(j) * sb0 + uint32_t(wrap(y0 - 1 - c1 + r, k.n1) * k.n0 + x0) * 2u + 16u * q;
+    } else {
+      const int r = min(lx >> 1, ROWS - 1), side = lx & 1;
+      const int xs = side ? (x0 + TX == k.n0 ? 0 : x0 + TX) : (x0 == 0 ? k.n0 - 2 : x0 - 2);
+      dv[t] = uint32_t(j) * sb0 + uint32_t(wrap(y0 - 1 - c1 + r, k.n1) * k.n0 + xs) * 2u;
     }
-    const int pr = min(tid, PAIRS - 1);
-    const int j = pr / ((TY + 2) * 2), r = (pr >> 1) % (TY + 2), side = pr & 1;
-    const int c1 = j / 3 - 1;
-    int ys = y0 - 1 - c1 + r;
-    ys = ys < 0 ? ys + k.n1 : (ys >= k.n1 ? ys - k.n1 : ys);
-    const int xs = side ? (x0 + TX == k.n0 ? 0 : x0 + TX) : (x0 == 0 ? k.n0 - 2 : x0 - 2);
-    voff[2] = j * sb0 + uint32_t(ys * k.n0 + xs) * 2u;
-    loff[2] = j * BOX + r * ROWB + 128 + 4 * side;
   }
-  struct Staged {
-    u32x4 a[3], b[3];
-    uint32_t pr[3];
-  };
-  // issues the loads of the stage of node plane p (direction i from plane p - c_iz)
-  auto stage_load = [&](int p, uint32_t sb, Staged& g) {
+  const int kind_off = side_kind ? SIDE : 1024 * kind;
+  // issues the direct loads of the stage of node plane p (direction j from
+  // plane p - c_jz) into stage stg
+  auto stage_load = [&](int p, unsigned char* stg) {
+    const char* base[3];  // slab of plane p - c_z, c_z = -1, 0, 1
 #pragma unroll
-    for (int grp = 0; grp < 3; ++grp) {
-      const Rsrc rs = rsrc(src + uint64_t(wrap(p - (grp - 1), k.n2)) * k.slab_bytes);
-      const uint32_t so = 9u * grp * sb;
-      g.a[grp] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[0], so, 0);
-      if (wave_b) g.b[grp] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[1], so, 0);
-      if (wave_p) g.pr[grp] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff[2], so, 0);
-    }
-  };
-  auto stage_store = [&](unsigned char* stg, const Staged& g) {
+    for (int c = 0; c < 3; ++c) base[c] = src + uint64_t(wrap(p - (c - 1), k.n2)) * k.slab_bytes;
+    if (dok) {
 #pragma unroll
-    for (int grp = 0; grp < 3; ++grp) {
-      *reinterpret_cast<u32x4*>(stg + 9 * grp * BOX + loff[0]) = g.a[grp];
-      if (wave_b) *reinterpret_cast<u32x4*>(stg + 9 * grp * BOX + loff[1]) = g.b[grp];
-      if (wave_p) *reinterpret_cast<uint32_t*>(stg + 9 * grp * BOX + loff[2]) = g.pr[grp];
+      for (int t = 0; t < ROUNDS; ++t) {
+        const int j = BPR * t + jw;
+        if (BPR * (t + 1) <= 27 || j < 27) {
+          // the z group of box j: fixed for a round whose boxes share it
+          const int g_lo = BPR * t / 9, g_hi = (BPR * t + BPR - 1) / 9;  // constants after unrolling
+          const int g = g_lo == g_hi ? g_lo : j / 9;
+          const Rsrc rs = rsrc(g == 0 ? base[0] : (g == 1 ? base[1] : base[2]));
+          const lds_ptr to = (lds_ptr)stg + j * BOX + kind_off;
+          if (side_kind) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, to, 4, dv[t], 0, 0, 0);
+          else __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, to, 16, dv[t], 0, 0, 0);
+        }
+      }
     }
   };
 
-  // next-plane anomaly of the node (ring) and of its halo node, from stage stg
+  // values, moments and anomalies of the node at a staged plane, and the
+  // halo node's anomaly into exchange buffer bo
   float drho, dj[3], qc[3] = {0.f, 0.f, 0.f}, qprev;
-  auto plane_anomalies = [&](const unsigned char* stg, int p, uint32_t sb, int bo, float& dr, float (&djo)[3],
-                             float (&q)[3]) {
-    node_moments(wall_side, stg, rb, p, sb, own, dr, djo);
+  Held held;  // values of the plane being relaxed
+  auto plane_pass = [&](const unsigned char* stg, int p, uint32_t sb, int bo, float& dr, float (&djo)[3],
+                        float (&q)[3], Held& keep) {
+    R v[Q];
+    node_values(wall_side, stg, rb, p, sb, own, v);
+#pragma unroll
+    for (int w = 0; w < 14; ++w)
+      keep.w[w] = uint32_t(v[2 * w]) | (2 * w + 1 < Q ? uint32_t(v[2 * w + 1]) << 16 : 0u);
+    moments(v, dr, djo);
     const float ir = recip(1.f + dr);
     q[0] = anomaly(k, 0, djo[0], ir);
     q[1] = anomaly(k, 1, djo[1], ir);
     q[2] = anomaly(k, 2, djo[2], ir);
     if (has_halo) {
+      R hv[Q];
+      node_values(h_side, stg, hb, p, sb, hown, hv);
       float hr, hj[3];
-      node_moments(h_side, stg, hb, p, sb, hown, hr, hj);
+      moments(hv, hr, hj);
       const float j = h_uref + (hax == 0 ? hj[0] : hj[1]);
       const float u = j * recip(1.f + hr);
       anom[hofs + bo * hstep + hslot] = j * h_anom - j * u * u;
@@ -961,47 +1008,47 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
     return zz < 0 ? zz + k.n2 : zz;
   };
 
-  // ---- prologue: the ring plane z0 - 1 and plane z0 ----
-  int bz, bz1, bfree = 0;
+  unsigned char* const st0 = smem;
+  unsigned char* const st1 = smem + STAGE;
+  // ---- prologue: the ring plane before the first, the first plane, and the
+  // loads of the second ----
+  stage_load(plane_index(zs - dir), st0);
+  stage_load(zs, st1);
+  drain_vm();
+  __syncthreads();
   {
-    Staged g;
-    stage_load(plane_index(z0 - 1), sb0, g);
-    stage_store(smem, g);
-    stage_load(z0, sb0, g);
-    stage_store(smem + STAGE, g);
-    __syncthreads();
+    R v[Q];
+    node_values(wall_side, st0, rb, plane_index(zs - dir), sb0, own, v);
     float dr, djp[3];
-    node_moments(wall_side, smem, rb, plane_index(z0 - 1), sb0, own, dr, djp);
+    moments(v, dr, djp);
     qprev = anomaly(k, 2, djp[2], recip(1.f + dr));
-    plane_anomalies(smem + STAGE, z0, sb0, 0, drho, dj, qc);
-    QX(0, sx_own) = qc[0];
-    QY(0, sy_own) = qc[1];
-    if (NSTAGE == 3) {
-      stage_load(plane_index(z0 + 1), sb0, g);
-      stage_store(smem + 2 * STAGE, g);
-      bz = 1, bz1 = 2, bfree = 0;
-    } else {
-      __syncthreads();  // plane z0 - 1's buffer is read
-      stage_load(plane_index(z0 + 1), sb0, g);
-      stage_store(smem, g);
-      bz = 1, bz1 = 0;
-    }
   }
+  plane_pass(st1, zs, sb0, 0, drho, dj, qc, held);
+  QX(0, sx_own) = qc[0];
+  QY(0, sy_own) = qc[1];
+  __syncthreads();  // the ring plane's stage is read
+  stage_load(plane_index(zs + dir), st0);
+  drain_vm();
   __syncthreads();
 
-  for (int z = z0; z < z1; ++z) {
-    const int b = (z - z0) & 1;
+  const float hz = dir > 0 ? k.hil[2] : -k.hil[2];  // z difference in march order
+  // One plane of the march: the stage of the next plane is `nxt` (complete),
+  // `fre` receives the plane after it; `cur` holds this plane's values and
+  // `held_next` receives the next plane's. The loop below is unrolled by two,
+  // so the roles of the stages and of the held values swap without copies.
+  auto plane_step = [&](int m, unsigned char* nxt, unsigned char* fre, const Held& cur, Held& held_next) {
+    const int z = zs + dir * m;
+    const int b = m & 1;
     // the array distance is made opaque per plane (see the kernel above)
     uint32_t sb = sb0;
     asm("" : "+s"(sb) : "s"(z));
-    // stage of plane z + 2: its loads fly while this plane is updated
-    Staged g;
-    stage_load(plane_index(z + 2), sb, g);
-    const unsigned char* s_z = smem + bz * STAGE;
+    // loads of the plane two on in march order fly while this plane is updated
+    stage_load(plane_index(z + 2 * dir), fre);
 
-    // next plane: own anomaly (closes the ring) and the halo's
+    // next plane: values (kept for its relaxation), own anomaly (closes the
+    // ring) and the halo's
     float drn, djn[3], qn[3];
-    plane_anomalies(smem + bz1 * STAGE, plane_index(z + 1), sb, b ^ 1, drn, djn, qn);
+    plane_pass(nxt, plane_index(z + dir), sb, b ^ 1, drn, djn, qn, held_next);
 
     // collision of plane z
     {
@@ -1011,38 +1058,17 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
       const float qym = wall_side == 1 ? -qc[1] : QY(b, sym);
       const float qyp = wall_side == -1 ? -qc[1] : QY(b, syp);
       Gd[1] = (qyp - qym) * k.hil[1];
-      Gd[2] = (qn[2] - qprev) * k.hil[2];
+      Gd[2] = (qn[2] - qprev) * hz;
       const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
-      auto emit = [&](int i, float o) { Store<S>::store(rd, own, i * sb, o); };
-      auto pulled = [&](auto side) {
-        constexpr int SIDE = decltype(side)::value;
-        return [&, z, sb](int i) {
-          return Store<S>::to_float(SIDE != 0 && cq<3>(i, 1) == SIDE ? bounce(z, sb, own, i) : pull_lds(s_z, rb, i));
-        };
-      };
-      if (WALLY && wall_side == 1) collide<3, FORCE>(k, drho, dj, Gd, pulled(SideLo()), emit);
-      else if (WALLY && wall_side == -1) collide<3, FORCE>(k, drho, dj, Gd, pulled(SideHi()), emit);
-      else collide<3, FORCE>(k, drho, dj, Gd, pulled(Side0()), emit);
+      collide<3, FORCE>(k, drho, dj, Gd, [&](int i) { return Store<S>::to_float(cur.get(i)); },
+                        [&](int i, float o) { Store<S>::store(rd, own, i * sb, o); });
     }
     QX(b ^ 1, sx_own) = qn[0];
     QY(b ^ 1, sy_own) = qn[1];
-    if (NSTAGE == 3) {
-      // into plane z - 1's buffer, free since the last barrier
-      stage_store(smem + bfree * STAGE, g);
-      __syncthreads();
-      const int t = bz;
-      bz = bz1;
-      bz1 = bfree;
-      bfree = t;
-    } else {
-      // into plane z's buffer, once every thread has relaxed plane z
-      __syncthreads();
-      stage_store(smem + bz * STAGE, g);
-      __syncthreads();
-      const int t = bz;
-      bz = bz1;
-      bz1 = t;
-    }
+    // this wave's direct loads are complete; after the barrier every wave's
+    // are, and every read of the stage just used is done
+    wait_vm_but_stores();
+    __syncthreads();
     drho = drn;
     dj[0] = djn[0];
     dj[1] = djn[1];
@@ -1051,6 +1077,16 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
     qc[0] = qn[0];
     qc[1] = qn[1];
     qc[2] = qn[2];
+  };
+  unsigned char* nx = st0;
+  unsigned char* fr = st1;
+  for (int m = 0; m < len; ++m) {
+    Held other;
+    plane_step(m, nx, fr, held, other);
+    held = other;
+    unsigned char* const t = nx;
+    nx = fr;
+    fr = t;
   }
 }
 

@@ -45,6 +45,11 @@ ARBITRARY = {
     "d3_min_periodic": dict(n=(3, 3, 3), T=0.3, omega=1.1),
     "d3_min_walls": dict(n=(5, 2, 4), T=0.5, omega=1.4, walls=(False, True, False)),
     "d3_control_stretched": dict(n=(32, 40, 24), lam=(2.0, 1.0, 1.0), T=1 / 3, omega=1.7, extended=False),
+    # an even number of chunks along the marched axis (eight of 4 rows; two of
+    # 16 planes): the last chunk marches down from the wall
+    "d2_walls_y_even_chunks": dict(n=(70, 32), T=0.4, omega=1.6, walls=(False, True), force=(5e-5, 0.0)),
+    "d3_walls_yz_two_chunks": dict(n=(20, 8, 32), T=0.4, omega=1.5, walls=(False, True, True),
+                                   force=(1e-4, 0.0, 0.0)),
 }
 
 
