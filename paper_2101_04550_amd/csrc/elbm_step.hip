@@ -1034,16 +1034,16 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
   const float hz = dir > 0 ? k.hil[2] : -k.hil[2];  // z difference in march order
   // One plane of the march: the stage of the next plane is `nxt` (complete),
   // `fre` receives the plane after it; `cur` holds this plane's values and
-  // `held_next` receives the next plane's. The loop below is unrolled by two,
-  // so the roles of the stages and of the held values swap without copies.
+  // `held_next` receives the next plane's.
   auto plane_step = [&](int m, unsigned char* nxt, unsigned char* fre, const Held& cur, Held& held_next) {
     const int z = zs + dir * m;
     const int b = m & 1;
     // the array distance is made opaque per plane (see the kernel above)
     uint32_t sb = sb0;
     asm("" : "+s"(sb) : "s"(z));
-    // loads of the plane two on in march order fly while this plane is updated
-    stage_load(plane_index(z + 2 * dir), fre);
+    // loads of the plane two on in march order fly while this plane is
+    // updated (on the last plane there is none that the tile reads)
+    if (m + 2 <= len) stage_load(plane_index(z + 2 * dir), fre);
 
     // next plane: values (kept for its relaxation), own anomaly (closes the
     // ring) and the halo's
