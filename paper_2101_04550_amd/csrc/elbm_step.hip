@@ -35,8 +35,11 @@
 //   step_kernel_lds -- LDS staged (16-bit storage, D3Q27, full 64 x 16 tiles,
 //                      x and z periodic, y periodic or bounce-back; 1024
 //                      threads): the block stages the rows its tile pulls
-//                      from with 16-byte loads and pulls from LDS.
+//                      from with direct buffer-to-LDS loads and pulls from
+//                      LDS.
 // Both run the same per-node arithmetic (collide) on the same stored values.
+// Tiles of odd chunks march down the slowest axis, so that two chunks read
+// the planes at their common face at about the same time.
 //
 // Arithmetic is FP32 on deviations h_i = f_i - w_i from the reference
 // equilibrium w_i = prod_a W_a[c_ia] (rho = 1, u = u_ref). Moments,
