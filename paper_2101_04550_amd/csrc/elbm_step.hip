@@ -669,11 +669,13 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     bool ghost_next, ghost2;
     plane(z + dir, ghost_next);
     const PlaneSrc s2 = src_planes(plane(z + 2 * dir, ghost2));
-    // The fetches and the moments below are issued on every plane and by every
-    // lane (lanes beyond a ragged edge work on a clamped node; at the end of a
-    // chunk or behind a wall the fetched plane goes unused), so that the code
-    // between a fetch and its use is straight-line and the waits for the loads
-    // count exactly the memory operations issued after them. The node's own
+    // The fetches and the moments below are issued by every lane (lanes
+    // beyond a ragged edge work on a clamped node; behind a wall the fetched
+    // plane goes unused), so that the code between a fetch and its use is
+    // straight-line and the waits for the loads count exactly the memory
+    // operations issued after them. Fetches of planes the tile never uses are
+    // skipped as a whole (a uniform test): the node's plane two on past the
+    // ring plane, the halo's plane two on past the last relaxed plane. The node's own
     // fetch precedes the halo's, whose branch then reuses its offsets.
     // next plane (always needed: its anomaly closes the ring)
     float drn, djn[3], qn[3] = {0.f, 0.f, 0.f};
@@ -684,7 +686,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       if (D == 3) qn[1] = anomaly(k, 1, djn[1], ir);
       qn[2] = anomaly(k, 2, djn[2], ir);
     }
-    P::fetch(sb, s2, no, near(s2), pf2);
+    if (m + 2 <= len) P::fetch(sb, s2, no, near(s2), pf2);
     // Memory drains (here, before the collision and after its stores): with
     // the next planes' reads left in flight, the halo and ring rows that
     // neighbouring tiles re-read drop out of L2 (about 18% more HBM reads
@@ -694,7 +696,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     // halo of the next plane (fetched one plane ahead), then the fetch two planes on
     if (has_halo) {
       halo_store(hp, b ^ 1);
-      P::fetch(sb, s2, hno, near(s2), hp);
+      if (m + 2 < len) P::fetch(sb, s2, hno, near(s2), hp);
     }
     const float qnext = ghost_next ? -qc[2] : qn[2];
 
