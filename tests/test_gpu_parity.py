@@ -277,6 +277,22 @@ def test_isotropy_stretched_on_gpu_and_control():
     assert abs(rc / 3.25 - 1) < 0.1
 
 
+@pytest.mark.parametrize("T,U0,predicted", [
+    (0.5, 0.0, 0.50),      # temperature away from T_L (Sec. 3.1: temperature dependence)
+    (1 / 3, 0.173, 0.933),  # advected rotated wave (Sec. 3.1: Galilean invariance lost)
+])
+def test_uncorrected_control_trends_on_gpu(T, U0, predicted):
+    """Negative control on the GPU kernels: the uncorrected product form's
+    viscosity follows the linearised limit without the counter term,
+    nu_eff / nu = 1 + (c_x + c_y) / (4T), c_a = lambda_a^2 - 3T - 3 U_a^2 (the
+    oracle pins the same law), while the extended model stays within 1%."""
+    rc = _gpu_viscosity((64, 64), (1.0, 1.0), T, U0, "f32", extended=False)
+    assert abs(rc / predicted - 1) < 0.1
+    assert abs(rc - 1) > 0.05
+    r = _gpu_viscosity((64, 64), (1.0, 1.0), T, U0, "f32")
+    assert abs(r - 1) < 1e-2
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_runs_are_deterministic_and_checkpoint_resumes_bitwise(storage):
     E = lib()
