@@ -599,14 +599,18 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     }
     return ps;
   };
-  // The tile or its halo touches a wall of a tiled axis (conservative).
-  const bool near_xy = WALL && ((k.w0 && (x0 <= 1 || x0 + TXW >= k.n0 - 1)) ||
-                                (k.w1 && (y0 <= 1 || y0 + TYR >= k.n1 - 1)));
-  auto near = [&](const PlaneSrc& ps) { return near_xy || ps.oz[0] || ps.oz[2]; };
-
   const int cx = active ? gx : 0, cy = active ? gy : 0;
   NodeOffs no;
   P::offsets(k, cx, cy, no);
+  // A wave takes the bounce-back fetch path (uniform) only if one of its
+  // lanes' nodes, resp. halo nodes, pulls from beyond a wall of a tiled axis,
+  // or the plane from beyond a wall of the marched axis; in a tile next to a
+  // y wall that is the wave of the wall row (and the x-halo lanes), not the
+  // whole tile.
+  auto beyond = [](const NodeOffs& o) { return o.ox[0] || o.ox[2] || o.oy[0] || o.oy[2]; };
+  const bool near_own = WALL && __ballot(beyond(no)) != 0;
+  const bool near_halo = WALL && __ballot(has_halo && beyond(hno)) != 0;
+  auto near = [&](const PlaneSrc& ps, bool xy) { return xy || ps.oz[0] || ps.oz[2]; };
   const uint32_t sb0 = uint32_t(Ld->pstride) * uint32_t(sizeof(T));
 
   // Populations in flight: while plane z is relaxed one set holds plane z,
@@ -624,12 +628,12 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     {
       float dr, djp[3];
       const PlaneSrc sp = src_planes(zp);
-      P::fetch(sb0, sp, no, near(sp), P2);
+      P::fetch(sb0, sp, no, near(sp, near_own), P2);
       P::moments(k, P2, dr, djp);
       qprev = anomaly(k, 2, djp[2], recip(1.f + dr));
     }
     const PlaneSrc s0 = src_planes(zs);
-    P::fetch(sb0, s0, no, near(s0), P0);
+    P::fetch(sb0, s0, no, near(s0, near_own), P0);
     P::moments(k, P0, drho, dj);
     {
       const float ir = recip(1.f + drho);
@@ -644,11 +648,11 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     }
     bool ghost1;
     const PlaneSrc s1 = src_planes(plane(zs + dir, ghost1));
-    P::fetch(sb0, s1, no, near(s1), P1);
+    P::fetch(sb0, s1, no, near(s1, near_own), P1);
     if (has_halo) {
-      P::fetch(sb0, s0, hno, near(s0), hp);
+      P::fetch(sb0, s0, hno, near(s0, near_halo), hp);
       halo_store(hp, 0);
-      P::fetch(sb0, s1, hno, near(s1), hp);
+      P::fetch(sb0, s1, hno, near(s1, near_halo), hp);
     }
   }
   __syncthreads();
@@ -686,7 +690,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       if (D == 3) qn[1] = anomaly(k, 1, djn[1], ir);
       qn[2] = anomaly(k, 2, djn[2], ir);
     }
-    if (m + 2 <= len) P::fetch(sb, s2, no, near(s2), pf2);
+    if (m + 2 <= len) P::fetch(sb, s2, no, near(s2, near_own), pf2);
     // Memory drains (here, before the collision and after its stores): with
     // the next planes' reads left in flight, the halo and ring rows that
     // neighbouring tiles re-read drop out of L2 (about 18% more HBM reads
@@ -696,7 +700,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     // halo of the next plane (fetched one plane ahead), then the fetch two planes on
     if (has_halo) {
       halo_store(hp, b ^ 1);
-      if (m + 2 < len) P::fetch(sb, s2, hno, near(s2), hp);
+      if (m + 2 < len) P::fetch(sb, s2, hno, near(s2, near_halo), hp);
     }
     const float qnext = ghost_next ? -qc[2] : qn[2];
 
