@@ -152,7 +152,8 @@ def central_difference(q, a, lam_a, wall, D):
     Periodic axis: neighbours wrap. Bounce-back axis (reading; the paper is
     silent on the gradient next to a wall): odd ghost about the halfway wall,
     q(-1) = -q(0) and q(n) = -q(n-1), since the anomaly is odd in the
-    wall-normal momentum, which vanishes at the wall.
+    wall-normal momentum, which vanishes at the wall. (Pinned: for a purely
+    wall-normal flow this is exactly the mirrored periodic continuation.)
     """
     ax = _axis(a, D)
     if not wall:

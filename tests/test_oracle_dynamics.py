@@ -181,6 +181,56 @@ def test_uncorrected_control_matches_linear_theory(n, lam, T, U0):
     assert abs(ratio - 1.0) > 1e-2 or abs(predicted - 1.0) < 1e-2
 
 
+@pytest.mark.parametrize("D", [2, 3])
+def test_wall_equals_mirror_for_wall_normal_flow(D):
+    """Pins the wall treatment, including the odd ghost of the anomaly (reading
+    R6, Sec. 2.3 eq. Paastar1 next to a wall), by an exact equivalence.
+
+    A purely wall-normal flow (u_x = u_z = 0, no x or z dependence) keeps its
+    populations symmetric under c_x -> -c_x and c_z -> -c_z, so halfway
+    bounce-back acts on it as a mirror. Between walls a distance H apart it is
+    then the same as the periodic flow on 2H rows that continues the state
+    mirrored (u_y reversed) beyond each wall; there the anomaly beyond the wall
+    is the mirrored node's, -Q~ of the wall row (Q~_y is odd in j_y). Both
+    lattices run the same steps and must agree to rounding on the H rows. A
+    wrong ghost (even, zero, one-sided), a wrong bounce direction or a wrong
+    wall position breaks the equality.
+    """
+    H, T, omega = 10, 0.45, 1.3
+    lam = (1.0, 1.5, 1.0)[:D]
+    nw = (3, H, 2)[:D]
+    npd = (3, 2 * H, 2)[:D]
+    walls = (False, True, False)[:D]
+    g = I.rng(42)
+    rho_y = 1.0 + 0.05 * g.standard_normal(H)
+    uy_y = 0.04 * g.standard_normal(H)
+    rho_m = np.concatenate([rho_y, rho_y[::-1]])
+    uy_m = np.concatenate([uy_y, -uy_y[::-1]])
+
+    def field(n, rho1, uy1):
+        shape = I.grid_shape(n)
+        bshape = [1] * D
+        bshape[D - 2] = n[1]
+        rho = np.broadcast_to(rho1.reshape(bshape), shape).copy()
+        u = np.zeros((D,) + shape)
+        u[1] = np.broadcast_to(uy1.reshape(bshape), shape)
+        return rho, u
+
+    pw = O.Params(n=nw, lam=lam, T=T, omega=omega, walls=walls)
+    pp = O.Params(n=npd, lam=lam, T=T, omega=omega)
+    fw = O.init_state(*field(nw, rho_y, uy_y), pw)
+    fp = O.init_state(*field(npd, rho_m, uy_m), pp)
+    ys = [slice(None)] * (D + 1)
+    ys[D - 1] = slice(0, H)  # rows 0 ... H - 1 of the population array (axis 0 is i)
+    for _ in range(40):
+        fw = O.step(fw, pw)
+        fp = O.step(fp, pp)
+    np.testing.assert_allclose(fw, fp[tuple(ys)], rtol=0, atol=1e-13)
+    # the flow has not died out: the comparison is not between two rest states
+    _, u = O.velocity(fw, pw)
+    assert np.abs(u[1]).max() > 1e-3
+
+
 def test_poiseuille_between_bounce_back_walls():
     """Steady force-driven flow: u(y) = g/(2 nu) (y + 1/2)(N_y - 1/2 - y), walls half a
     node outside the first and last rows (textbook closed form for the halfway rule)."""
