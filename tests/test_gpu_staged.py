@@ -109,3 +109,50 @@ def test_kernel_choice():
     info = lat.kernel_info()
     assert info["kernel"] == "register" and info["tile"][:2] == (64, 8) and info["tiles"] >= 1
     lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_walls_equal_mirrored_periodic_lattice(storage):
+    """The wall path of the GPU kernels against their own periodic path: a
+    purely wall-normal flow between y walls (16 rows) evolves like the
+    periodic flow on 32 rows that continues it mirrored, u_y reversed (the
+    equivalence the oracle pins for its wall treatment). FP32 runs the
+    register-pull kernel, FP16 / BF16 the LDS-staged one on both lattices.
+    The two lattices add the same values in different orders (the mirrored
+    nodes hold permuted populations), so they agree to rounding: 2e-6 in
+    FP32 after 20 steps, four units of the last stored place in 16 bits."""
+    E = lib()
+    H, T, omega = 16, 0.45, 1.3
+    g = np.random.default_rng(7)
+    rho_y = 1.0 + 0.05 * g.standard_normal(H)
+    uy_y = 0.04 * g.standard_normal(H)
+
+    def make(n, walls, rho1, uy1):
+        p = O.Params(n=n, T=T, omega=omega, walls=walls)
+        shape = (n[2], n[1], n[0])
+        rho = np.broadcast_to(rho1.reshape(1, -1, 1), shape).copy()
+        u = np.zeros((3,) + shape)
+        u[1] = np.broadcast_to(uy1.reshape(1, -1, 1), shape)
+        lat = E.Lattice(params_for(p, storage))
+        lat.set_populations(O.init_state(rho, u, p))
+        return lat
+
+    lw = make((64, H, 8), (False, True, False), rho_y, uy_y)
+    lp = make((64, 2 * H, 8), (False, False, False), np.concatenate([rho_y, rho_y[::-1]]),
+              np.concatenate([uy_y, -uy_y[::-1]]))
+    want = "register" if storage == "f32" else "staged"
+    assert lw.kernel_info()["kernel"] == want and lp.kernel_info()["kernel"] == want
+    lw.step(20)
+    lp.step(20)
+    fw = lw.populations()
+    fp = lp.populations()[:, :, :H, :]
+    w = O.reference_weights(O.Params(n=(64, H, 8), T=T, omega=omega)).reshape((-1, 1, 1, 1))
+    err = np.abs(fw - fp).max()
+    if storage == "f32":
+        assert err <= 2e-6
+    else:
+        hmax = np.abs(fw - w).max()
+        assert err <= 4 * EPS[storage] * hmax
+    # the flow is still there
+    _, u = lw.fields()
+    assert np.abs(u[1]).max() > 1e-3
