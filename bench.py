@@ -60,6 +60,8 @@ def parse_args():
                     help="only run a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the served mixed stream (0: skip the serving leg)")
+    ap.add_argument("--channel-only", action="store_true",
+                    help="only the 384x192x192 channel leg (FP32 and FP16), one JSON line: for per-kernel profiles")
     ap.add_argument("--hit-only", action="store_true",
                     help="only the 256^3 turbulence legs (no D2Q9 or serving leg): for per-kernel profiles")
     return ap.parse_args()
@@ -309,10 +311,13 @@ def main():
     args = parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
-              "(the lattice is not sharded across GPUs in this build)", file=sys.stderr)
+              "(a lattice runs on one GPU; sharding it across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.channel_only:
+        print(json.dumps({"channel": channel_leg()}), flush=True)
         return
     import torch
 

@@ -43,7 +43,7 @@ extern "C" {
 typedef enum elbm_status {
   ELBM_OK = 0,
   ELBM_EINVAL = 1,        /* a parameter is out of range or inconsistent      */
-  ELBM_EUNSUPPORTED = 2,  /* valid request this build does not implement      */
+  ELBM_EUNSUPPORTED = 2,  /* valid request the library does not implement    */
   ELBM_ENOMEM = 3,        /* the device buffer is smaller than required       */
   ELBM_EDEVICE = 4,       /* a HIP runtime call failed (text in last_error)   */
   ELBM_EUNSTABLE = 5      /* diagnostics saw a non-finite value or rho <= 0   */
