@@ -339,3 +339,26 @@ def test_error_paths():
     other = E.Lattice(params_for(O.Params(n=(64, 32), T=1 / 3, omega=1.5)))
     with pytest.raises(E.ElbmError):
         other.load(lat.save())
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 3])
+def test_short_chunks_match_oracle(chunk, monkeypatch):
+    """Tiles of 1, 2 or 3 planes (forced): the prologue, the ring planes at
+    both chunk ends, the downward march of odd chunks and the skipped fetches
+    of unused planes all act on nearly every plane. Walls on z put chunk ends
+    next to the wall ghosts; one and ten steps from an arbitrary state against
+    the oracle, as for the other lattices."""
+    monkeypatch.setenv("ELBM_CHUNK", str(chunk))
+    E = lib()
+    p = O.Params(n=(20, 16, 9), lam=(1.0, 1.5, 1.0), T=0.45, omega=1.5, walls=(False, False, True),
+                 force=(5e-5, 0.0, -3e-5))
+    f0 = random_state(p, seed=91 + chunk)
+    lat = E.Lattice(params_for(p))
+    assert lat.kernel_info()["tile"][2] == chunk
+    lat.set_populations(f0)
+    g0 = lat.populations()
+    lat.step(1)
+    o1 = O.step(g0, p)
+    assert np.abs(lat.populations() - o1).max() <= 2e-7
+    lat.step(9)
+    assert dev_rel_l2(lat.populations(), O.run(o1, p, 9), p) <= 1e-5

@@ -156,3 +156,25 @@ def test_walls_equal_mirrored_periodic_lattice(storage):
     # the flow is still there
     _, u = lw.fields()
     assert np.abs(u[1]).max() > 1e-3
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 3])
+def test_staged_short_chunks_equal_register_pull(chunk, monkeypatch):
+    """The staged kernel with tiles of 1, 2 or 3 planes (forced): stage loads
+    skipped on a tile's last plane, downward march of odd chunks, y walls;
+    against the register-pull kernel on the same lattice after five steps, to
+    the last-bit rounding bound of the equality test above."""
+    monkeypatch.setenv("ELBM_CHUNK", str(chunk))
+    p = O.Params(n=(64, 16, 9), lam=(2.0, 1.0, 1.0), T=0.5, omega=1.7, walls=(False, True, False),
+                 force=(1e-5, 0.0, 0.0))
+    f0 = random_state(p, seed=33 + chunk)
+    ls = lattice(p, "f16", True, f0)
+    lr = lattice(p, "f16", False, f0)
+    assert ls.kernel_info()["kernel"] == "staged" and ls.kernel_info()["tile"][2] == chunk
+    assert lr.kernel_info()["kernel"] == "register"
+    ls.step(5)
+    lr.step(5)
+    fs, fr = ls.populations(), lr.populations()
+    w = O.reference_weights(p).reshape((-1, 1, 1, 1))
+    hmax = np.abs(fr - w).max()
+    assert np.abs(fs - fr).max() <= 2 * EPS["f16"] * hmax
