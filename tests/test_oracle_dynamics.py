@@ -284,3 +284,106 @@ def test_diagnostics_closed_forms():
     assert abs(d.ke - 0.5 * (0.05 ** 2 + A * A / 2)) < 1e-16
     assert abs(d.mass - 64 * 64) < 1e-10
     assert d.nan_count == 0
+
+
+def _magic_poiseuille(D, ny=8, g=1e-5):
+    """Force-driven flow between halfway bounce-back walls at the relaxation time
+    tau = 1/omega = 1/2 + sqrt(3)/4, started from the Navier-Stokes parabola."""
+    tau = 0.5 + math.sqrt(3.0) / 4.0
+    n = (3, ny) if D == 2 else (3, ny, 3)
+    walls = (False, True) + ((False,) if D == 3 else ())
+    p = O.Params(n=n, T=1.0 / 3.0, omega=1.0 / tau, walls=walls, force=(g,) + (0.0,) * (D - 1))
+    grid = tuple(reversed(n))
+    y = np.arange(ny) + 0.5  # distance from the lower wall, half a node below row 0
+    exact = g / (2.0 * p.nu) * y * (ny - y)
+    u = np.zeros((D,) + grid)
+    shape = [1] * D
+    shape[D - 2] = ny
+    u[0] = exact.reshape(shape)
+    f = O.run(O.init_state(np.ones(grid), u, p), p, 1200)
+    return p, f, exact
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_poiseuille_exact_at_magic_relaxation_reports_half_force_velocity(D):
+    """Pins the bounce-back walls, the body force and the reported velocity
+    (j + rho g/2)/rho together against the Navier-Stokes solution
+    u(y) = g/(2 nu) y (2H - y), y the distance from a wall half a node outside
+    the first row. For LBGK with halfway bounce-back the steady unidirectional
+    flow carries no wall slip exactly when tau = 1/2 + sqrt(3)/4 (a property of
+    the bounce-back rule for LBGK, independent of the lattice); here
+    T = T_L = 1/3 and lambda = 1, where the product form is the standard
+    equilibrium for a unidirectional flow and the anomaly gradient vanishes.
+    The steady state then matches the parabola to round-off, but only with the
+    half-force velocity: the post-collision momentum j'/rho (or the pre-force
+    j/rho) is off by g/2 everywhere, about 1% of the centreline value."""
+    p, f, exact = _magic_poiseuille(D)
+    rho, u = O.velocity(f, p)
+    ux = np.moveaxis(u[0], D - 2, 0).reshape(exact.size, -1)
+    assert np.abs(ux - exact[:, None]).max() <= 1e-10 * exact.max()
+    # the other conventions are not the steady solution
+    _, jpost = O.moments(f, p.c, p.lam)
+    upost = np.moveaxis(jpost[0] / rho, D - 2, 0).reshape(exact.size, -1)
+    assert np.abs(upost - exact[:, None]).min() > 0.4 * p.force[0]
+    assert np.abs(u[1:]).max() < 1e-15
+
+
+def _vorticity_closed_form_case(walls):
+    """3-D velocity field whose central-difference curl is known node by node.
+
+    Periodic: u = a_c cos(k.x + phi_c) per component c (phases differ, so the
+    curl is not a plane wave). Walls on y: u_c = a_c sin(k_y Y) cos(k_x X + k_z Z + phi_c)
+    with Y = (y + 1/2) lam_y and k_y = pi m / (n_y lam_y): odd about both halfway
+    walls, so the no-slip ghost u(-1) = -u(0), u(n) = -u(n - 1) is this same
+    function continued. The central difference along a of sin/cos(k_a x_a) is
+    sin(k_a lam_a)/lam_a times the derivative's cos/-sin, exactly."""
+    n, lam = (10, 12, 8), (1.4, 1.0, 2.0)
+    p = O.Params(n=n, lam=lam, T=0.5, omega=1.5, walls=(False, walls, False))
+    X, Y, Z = I.coords(n, lam)
+    kx, kz = 2 * math.pi * 2 / (n[0] * lam[0]), -2 * math.pi / (n[2] * lam[2])
+    a = (0.03, -0.02, 0.025)
+    ph = (0.3, 1.7, -0.9)
+    kp = lambda k, l: math.sin(k * l) / l  # noqa: E731 -- discrete wavenumber
+    if not walls:
+        ky = 2 * math.pi / (n[1] * lam[1])
+        arg = [kx * X + ky * Y + kz * Z + ph[c] for c in range(3)]
+        u = np.stack([a[c] * np.cos(arg[c]) for c in range(3)])
+        # d_b u_c = -a_c sin(arg_c) k'_b
+        du = [[-a[c] * np.sin(arg[c]) * kp(k, lam[b]) for b, k in enumerate((kx, ky, kz))] for c in range(3)]
+    else:
+        ky = math.pi * 2 / (n[1] * lam[1])
+        Yh = Y + 0.5 * lam[1]
+        arg = [kx * X + kz * Z + ph[c] for c in range(3)]
+        u = np.stack([a[c] * np.sin(ky * Yh) * np.cos(arg[c]) for c in range(3)])
+        du = [[-a[c] * np.sin(ky * Yh) * np.sin(arg[c]) * kp(kx, lam[0]),
+               a[c] * np.cos(ky * Yh) * np.cos(arg[c]) * kp(ky, lam[1]),
+               -a[c] * np.sin(ky * Yh) * np.sin(arg[c]) * kp(kz, lam[2])] for c in range(3)]
+    wx = du[2][1] - du[1][2]
+    wy = du[0][2] - du[2][0]
+    wz = du[1][0] - du[0][1]
+    return p, u, wx * wx + wy * wy + wz * wz
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_vorticity_3d_closed_form(walls):
+    """The 3-D enstrophy integrand |curl u|^2 (Sec. 3.3) node by node against the
+    closed-form central-difference curl: all three components nonzero, unequal
+    spacings on the three axes, and (walls) the no-slip ghost on the y walls."""
+    p, u, exact = _vorticity_closed_form_case(walls)
+    np.testing.assert_allclose(O.vorticity_sq(u, p), exact, rtol=1e-12, atol=1e-18)
+    assert exact.max() - exact.min() > 0.2 * exact.max()  # not a constant field
+
+
+def test_enstrophy_of_plane_wave_is_half_discrete_cross_product():
+    """<|curl u|^2> of u = a sin(k.x) is |k' x a|^2 / 2 with k'_b = sin(k_b lam_b)/lam_b."""
+    n, lam = (12, 10, 9), (2.0, 1.0, 1.4)
+    p = O.Params(n=n, lam=lam, T=0.5, omega=1.5)
+    X, Y, Z = I.coords(n, lam)
+    k = (2 * math.pi / (n[0] * lam[0]), 2 * math.pi * 2 / (n[1] * lam[1]), -2 * math.pi / (n[2] * lam[2]))
+    a = np.array([0.01, 0.02, -0.015])
+    s = np.sin(k[0] * X + k[1] * Y + k[2] * Z)
+    u = np.stack([a[c] * s for c in range(3)])
+    kd = np.array([math.sin(k[b] * lam[b]) / lam[b] for b in range(3)])
+    f = O.init_state(np.ones(s.shape), u, p)
+    d = O.diagnostics(f, p)
+    assert abs(d.enstrophy / (0.5 * float(np.cross(kd, a) @ np.cross(kd, a))) - 1) < 1e-10
