@@ -68,7 +68,9 @@ enum { ELBM_STORE_F32 = 0, ELBM_STORE_F16 = 1, ELBM_STORE_BF16 = 2 };
  *  omega        relaxation parameter in (0, 2); kinematic viscosity
  *               nu = (1/omega - 1/2) T (Sec. 2.1, eq. nu).
  *  u_adv[3]     advection velocity added to the initial velocity field by
- *               elbm_init, and reference velocity of the stored deviations.
+ *               elbm_init, and reference velocity of the stored deviations;
+ *               must be 0 on a lattice with bounce-back walls
+ *               (ELBM_EUNSUPPORTED otherwise).
  *  force[3]     constant body-force acceleration g (Sec. 3.5), applied by the
  *               exact-difference method F_i = f^eq_i(rho, u + g) - f^eq_i(rho, u).
  *  bc[3]        per axis ELBM_BC_PERIODIC or ELBM_BC_BOUNCEBACK (halfway
@@ -160,7 +162,8 @@ const char* elbm_last_error(void);
  * every axis; at least 3 nodes on a periodic axis, 2 on a wall axis; at most
  * 2^31 - 1 nodes, and Q times the nodes of one plane across the slowest axis
  * (n_x n_y for D3Q27, n_x for D2Q9) times the element size below 2^32 bytes).
- * Returns ELBM_EINVAL or ELBM_EUNSUPPORTED with a message, else ELBM_OK. */
+ * Returns ELBM_EINVAL or ELBM_EUNSUPPORTED (bounce-back walls together with a
+ * nonzero u_adv) with a message, else ELBM_OK. */
 int32_t elbm_validate(const elbm_params* params);
 
 /* Device bytes a lattice needs: two population buffers (ping-pong) of about

@@ -85,6 +85,23 @@ int class_of(int D, int storage, bool wall, bool force, bool staged) {
   return ((((D == 3) * 3 + storage) * 2 + (wall ? 1 : 0)) * 2 + (force ? 1 : 0)) * 2 + (staged ? 1 : 0);
 }
 
+// The kernel class of index c (inverse of class_of).
+struct ClassKey {
+  int D, storage;
+  bool wall, force, staged;
+};
+ClassKey class_key(int c) {
+  return ClassKey{c >= kClasses / 2 ? 3 : 2, (c / 8) % 3, (c / 4) % 2 == 1, (c / 2) % 2 == 1, c % 2 == 1};
+}
+
+// Persistent grid of a batched launch: a power of two >= the tiles (capped),
+// so that one captured graph serves every mix of the same size class.
+int batch_grid(int64_t tiles) {
+  int64_t g = 64;
+  while (g < tiles && g < 4096) g *= 2;
+  return int(g);
+}
+
 // Whether a lattice takes the LDS-staged step kernel: D3Q27 with 16-bit
 // storage, full tiles (n_x % 64 == 0, n_y % kRowsStaged == 0), x and z
 // periodic, y periodic or bounce-back. ELBM_STAGED=0 forces the register-pull
@@ -112,13 +129,6 @@ struct Layout {
   size_t off_hdr = 0, off_desc = 0, off_partials = 0, off_hist = 0, off_last = 0, off_count = 0, total = 0;
   int32_t capacity = 0;
 };
-
-int64_t stride_pad() {
-  const char* s = std::getenv("ELBM_STRIDE_PAD");
-  if (!s) return 0;
-  const long long v = std::atoll(s);
-  return v > 0 ? v : 0;
-}
 
 int32_t check(const elbm_params* p) {
   if (!p) return fail(ELBM_EINVAL, "params is NULL");
@@ -161,6 +171,21 @@ int32_t check(const elbm_params* p) {
   }
   if (!finite3(p->u_adv) || !finite3(p->force) || !finite3(p->mode_k) || !finite3(p->mode_dir))
     return fail(ELBM_EINVAL, "u_adv, force, mode_k, mode_dir must be finite");
+  {
+    // A bounced population is the node's own post-collision population of
+    // the opposite direction; stored as a deviation from the reference
+    // equilibrium w(u_adv), it would need the correction w_opp - w_i, which
+    // is nonzero whenever u_adv is. The kernels do not apply it, so walls
+    // require the rest state as reference.
+    bool wall = false, adv = false;
+    for (int a = 0; a < D; ++a) {
+      wall = wall || p->bc[a] == ELBM_BC_BOUNCEBACK;
+      adv = adv || p->u_adv[a] != 0.0;
+    }
+    if (wall && adv)
+      return fail(ELBM_EUNSUPPORTED, "bounce-back walls require u_adv == 0 (the deviation reference of a walled "
+                                     "lattice is the rest equilibrium)");
+  }
   if (p->storage < ELBM_STORE_F32 || p->storage > ELBM_STORE_BF16)
     return fail(ELBM_EINVAL, "storage must be ELBM_STORE_F32, ELBM_STORE_F16 or ELBM_STORE_BF16");
   if (p->extended != 0 && p->extended != 1) return fail(ELBM_EINVAL, "extended must be 0 or 1");
@@ -178,7 +203,7 @@ Layout layout_of(const elbm_params* p) {
   L.es = p->storage == ELBM_STORE_F32 ? 4 : 2;
   L.plane = L.D == 3 ? int64_t(p->n[0]) * p->n[1] : p->n[0];
   L.nplanes = L.D == 3 ? p->n[2] : p->n[1];
-  L.pstride = int64_t(align_up(size_t(L.plane), 64)) + stride_pad();
+  L.pstride = int64_t(align_up(size_t(L.plane), 64));
   // (a small tail keeps vector loads near the end of the last slab in range)
   L.pop_bytes = align_up(size_t(L.nplanes) * size_t(L.Q) * size_t(L.pstride) * L.es + 1024, 4096);
   L.capacity = p->diag_every > 0 ? p->diag_capacity : 0;
@@ -753,11 +778,7 @@ int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps
       HIPCHK(hipMalloc(reinterpret_cast<void**>(&p), tbytes));
       b->dev_tables[c] = p;
     }
-    // persistent grid: a power of two >= the tiles (capped), so that one
-    // captured graph serves every mix of the same size class
-    int64_t g = 64;
-    while (g < base && g < 4096) g *= 2;
-    grids.push_back(int(g));
+    grids.push_back(batch_grid(base));
   }
   // order the device work after what is pending on the caller's and the lattices' streams
   HIPCHK(hipEventRecord(b->entry, b->caller));
@@ -779,14 +800,10 @@ int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps
       int gi = 0;
       for (int c = 0; c < kClasses; ++c) {
         if (!(mask & (uint64_t(1) << c))) continue;
-        const int D = c >= kClasses / 2 ? 3 : 2;
-        const int storage = (c / 8) % 3;
-        const bool wall = (c / 4) % 2;
-        const bool force = (c / 2) % 2;
-        const bool staged = c % 2;
+        const ClassKey ck = class_key(c);
         const auto* hdr = reinterpret_cast<const TableHeader*>(b->dev_tables[c]);
         const auto* tab = reinterpret_cast<const LatticeDesc*>(b->dev_tables[c] + hbytes);
-        HIPCHK(launch_step(D, storage, wall, force, staged, hdr, tab, sub, grids[gi++], st));
+        HIPCHK(launch_step(ck.D, ck.storage, ck.wall, ck.force, ck.staged, hdr, tab, sub, grids[gi++], st));
       }
     }
     return ELBM_OK;

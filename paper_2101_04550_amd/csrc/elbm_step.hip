@@ -359,7 +359,21 @@ __device__ __forceinline__ void load_const(const LatticeDesc* __restrict__ Ld, u
 // (already divided by 2 lambda_a) and the pulled values hval(i) (storage
 // scale), emits the relaxed and forced populations o_i in storage scale
 // through emit(i, o_i).
-template <int D, bool FORCE, class HV, class EMIT>
+//
+// ACC (FP32 storage) keeps the FP32 rounding error relative to small
+// quantities in two places, where 16-bit storage, whose own rounding is
+// 2^13 times coarser, gains nothing from it:
+// * the velocity deviation x / rho, x = dj - drho u_ref, is formed as
+//   x - (x drho) / rho: the rounding of rho = 1 + drho and of its reciprocal
+//   then only touches the small correction term (x / rho directly carries a
+//   relative error of about one ulp of rho into every velocity, and the
+//   relaxation turns a velocity error into a momentum error of about omega
+//   times that, every step);
+// * the relaxation is applied to the non-equilibrium part,
+//   o = e + (1 - w)(h - e) with e = scale (f* - w) and h - e exact while the
+//   node is near equilibrium, instead of (1 - w) h + w e, whose two terms
+//   nearly cancel when w is close to 2 (one more operation per population).
+template <int D, bool FORCE, bool ACC, class HV, class EMIT>
 __device__ __forceinline__ void collide(const TileConst& k, float drho, const float (&dj)[3], const float (&Gd)[3],
                                         HV hval, EMIT emit) {
   constexpr int Q = D == 3 ? 27 : 9;
@@ -372,7 +386,8 @@ __device__ __forceinline__ void collide(const TileConst& k, float drho, const fl
       du[a] = 0.f;
       dP[a] = 0.f;
     } else {
-      du[a] = (dj[a] - drho * k.uref[a]) * ir;
+      const float x = dj[a] - drho * k.uref[a];
+      du[a] = ACC ? __builtin_fmaf(-(x * drho), ir, x) : x * ir;
       const float u = k.uref[a] + du[a];
       dP[a] = du[a] * (u + k.uref[a]) + k.coef * Gd[a] * ir;
     }
@@ -408,15 +423,17 @@ __device__ __forceinline__ void collide(const TileConst& k, float drho, const fl
   // Relaxation (Sec. 2.1, eq. LBGK) in storage scale,
   //   o_i = (1 - w) h_i + w scale (f*_i - w_i) (+ scale F_i),
   // with f*_i - w_i = drho B_i + dB_i from the product deviation. The
-  // factor w scale and the (c_x, c_y) partial products are applied once per
-  // node: w scale (drho X + dX) p_z + W_x W_y (w scale d_z) for D3Q27,
-  // w scale (drho W~_x + d_x) p_y + W_x (w scale d_y) for D2Q9.
-  const float drs = k.oms * drho;
+  // factor m = w scale (ACC: m = scale, the relaxation follows) and the
+  // (c_x, c_y) partial products are applied once per node:
+  // m (drho X + dX) p_z + W_x W_y (m d_z) for D3Q27,
+  // m (drho W~_x + d_x) p_y + W_x (m d_y) for D2Q9.
+  const float mfold = ACC ? k.scale : k.oms;
+  const float drs = mfold * drho;
   float ds[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ds[a][c] = k.oms * d[a][c];
+    for (int c = 0; c < 3; ++c) ds[a][c] = mfold * d[a][c];
   float A[3][3];  // [c_x][c_y]; D2Q9 uses [c_x][1]
 #pragma unroll
   for (int c0 = 0; c0 < 3; ++c0)
@@ -448,7 +465,8 @@ __device__ __forceinline__ void collide(const TileConst& k, float drho, const fl
   for (int i = 0; i < Q; ++i) {
     const int c0 = cq<D>(i, 0) + 1, c1 = cq<D>(i, 1) + 1, c2 = cq<D>(i, 2) + 1;
     const float Wc = D == 3 ? k.WW[c0][c1] : k.W[0][c0];
-    float o = A[c0][c1] * p[2][c2] + Wc * ds[2][c2];
+    const float fe = A[c0][c1] * p[2][c2] + Wc * ds[2][c2];
+    float o = ACC ? 0.f : fe;
     if (FORCE) {
       if (D == 3) {
         const float Y = sx[c0] * pe[1][c1];
@@ -458,7 +476,12 @@ __device__ __forceinline__ void collide(const TileConst& k, float drho, const fl
         o += ex[c0] * qz[c2] + sx[c0] * e[2][c2];
       }
     }
-    emit(i, k.om1 * hval(i) + o);
+    if (ACC) {
+      const float hv = hval(i);
+      emit(i, __builtin_fmaf(k.om1, hv - fe, fe) + o);
+    } else {
+      emit(i, k.om1 * hval(i) + o);
+    }
   }
 }
 
@@ -720,7 +743,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       Gd[2] = (qnext - qprev) * hz;
 
       const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
-      collide<D, FORCE>(k, drho, dj, Gd, [&](int i) { return h.get(i); },
+      collide<D, FORCE, S == 0>(k, drho, dj, Gd, [&](int i) { return h.get(i); },
                         [&](int i, float o) { Store<S>::store(rd, no.own, i * sb, o); });
     }
     drain_vm();
@@ -1069,7 +1092,7 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
       Gd[1] = (qyp - qym) * k.hil[1];
       Gd[2] = (qn[2] - qprev) * hz;
       const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
-      collide<3, FORCE>(k, drho, dj, Gd, [&](int i) { return Store<S>::to_float(cur.get(i)); },
+      collide<3, FORCE, S == 0>(k, drho, dj, Gd, [&](int i) { return Store<S>::to_float(cur.get(i)); },
                         [&](int i, float o) { Store<S>::store(rd, own, i * sb, o); });
     }
     QX(b ^ 1, sx_own) = qn[0];

@@ -204,7 +204,10 @@ class Lattice:
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             if buffer is None:
-                buffer = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+                # allocated for the lattice's stream (torch's allocator ties
+                # a block to the stream it is allocated on)
+                with torch.cuda.stream(self.stream):
+                    buffer = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
             self.buffer = buffer
             h = C.c_void_p()
             _check(_lib.elbm_create(C.byref(params), C.c_void_p(buffer.data_ptr()), buffer.numel(),

@@ -67,6 +67,8 @@ class Result:
     enstrophy: float
     min_rho: float
     checksum: str
+    rho: np.ndarray = None  # final fields, kept when the server is asked to (keep_fields)
+    u: np.ndarray = None
 
     @property
     def latency(self):
@@ -91,7 +93,7 @@ class Server:
     """Admission by device footprint, resident lattices, graph-replayed fused rounds."""
 
     def __init__(self, pool_bytes: int, max_slots: int = 64, quantum: int = 100, use_graph: bool = True,
-                 checksums: bool = False):
+                 checksums: bool = False, keep_fields: bool = False):
         import torch
 
         self.torch = torch
@@ -100,7 +102,12 @@ class Server:
         self.quantum = int(quantum)
         self.use_graph = bool(use_graph)
         self.checksums = bool(checksums)
+        self.keep_fields = bool(keep_fields)
         self.batch = E.Batch(self.max_slots)
+        # one stream per resident lattice: its upload at admission is ordered
+        # after nothing else, so it runs while a round is on the GPU (the
+        # batch orders each round after the lattices' streams itself)
+        self.streams = [torch.cuda.Stream() for _ in range(self.max_slots)]
         self.used = 0
         self.rounds = 0
         self.peak_used = 0
@@ -112,11 +119,17 @@ class Server:
     def _admit(self, req: Request, now: float):
         p = req.params()
         nbytes = E.query_bytes(p)
-        lat = E.Lattice(p)
+        stream = self.streams.pop()
+        lat = E.Lattice(p, stream=stream)
         lat.init(req.rho, req.u)
         self.used += nbytes
         self.peak_used = max(self.peak_used, self.used)
         return _Active(req, lat, req.steps, now, nbytes)
+
+    def _release(self, a):
+        a.lat.close()
+        self.streams.append(a.lat.stream)
+        self.used -= a.nbytes
 
     def fits(self, req: Request, nactive: int) -> bool:
         return nactive < self.max_slots and self.used + E.query_bytes(req.params()) <= self.pool_bytes
@@ -167,10 +180,10 @@ class Server:
                     continue
                 d = a.lat.diag(check=False)
                 cs = state_checksum(a.lat) if self.checksums else ""
+                rho, u = a.lat.fields() if self.keep_fields else (None, None)
                 results[a.req.rid] = Result(a.req.rid, a.req.arrival, a.admitted, done_at, a.req.steps,
-                                            a.req.cells, d["ke"], d["enstrophy"], d["min_rho"], cs)
-                a.lat.close()
-                self.used -= a.nbytes
+                                            a.req.cells, d["ke"], d["enstrophy"], d["min_rho"], cs, rho, u)
+                self._release(a)
             active = still + joined
             self.peak_slots = max(self.peak_slots, len(active))
         self.makespan = clock() - t0

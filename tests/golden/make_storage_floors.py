@@ -85,8 +85,32 @@ def floors(name, storages=STORAGES, steps=STEPS):
     return name, out
 
 
+VISC_CASES = tuple((T, st, n) for T in (1.0 / 3.0, 0.5) for st in ("f16",) for n in (500, 1000))
+
+
+def viscosity_floor(args):
+    """Fitted nu / (1/omega - 1/2) T of the advected axis-aligned wave (64^2,
+    a0 = 0.01, U0 = 0.1 as the deviation reference, omega = 1.8; Sec. 3.1)
+    over n steps, with the state rounded to the storage format after every
+    step: the part of the viscosity error the format alone causes."""
+    T, st, nsteps = args
+    fld = I.shear_wave_axis((64, 64), U0=0.0, A=0.01)
+    p = O.Params(n=(64, 64), T=T, omega=1.8)
+    uadv = (0.1, 0.0)
+    w = O.reference_weights(p, uadv).reshape((-1, 1, 1))
+    f = round_state(O.init_state(fld.rho, fld.u, p, u_adv=uadv), w, st)
+    ts, amps = [], []
+    for s in range(1, nsteps + 1):
+        f = round_state(O.step(f, p), w, st)
+        if s % 5 == 0:
+            ts.append(s)
+            amps.append(abs(O.diagnostics(f, p, fld.mode_k, fld.mode_dir).mode))
+    return args, O.fit_decay_rate(ts, amps, 50) / fld.mode_k[0] ** 2 / p.nu
+
+
 def main():
     with ProcessPoolExecutor(max_workers=min(len(CASES), os.cpu_count() or 1)) as ex:
+        visc = list(ex.map(viscosity_floor, VISC_CASES))
         results = dict(ex.map(floors, CASES))
     lines = [
         "# Storage floors: rel-L2 per velocity component after 100 steps between the FP64 oracle",
@@ -102,6 +126,9 @@ def main():
             else:
                 for a, v in enumerate(val):
                     lines.append(f"{name} {key} u{a} {v:.6e}")
+    lines.append("# viscosity fits (Sec. 3.1): case storage nu<steps> fitted-nu / nu")
+    for (T, st, nsteps), r in visc:
+        lines.append(f"visc_cfg1_T{0.5 if T == 0.5 else 0.33}_uadv {st} nu{nsteps} {r:.6e}")
     with open(OUT, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(OUT)

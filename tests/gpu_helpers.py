@@ -51,3 +51,47 @@ def dev_rel_l2(fg, fo, p, u_ref=None):
     """rel-L2 of population deviations from the reference weights."""
     w = O.reference_weights(p, u_ref).reshape((-1,) + (1,) * p.D)
     return rel_l2(fg - w, fo - w)
+
+
+# ---- parity bounds from the storage floors, and a record of what was measured ----
+
+_FLOORS = None
+MEASURED = []  # dicts written to $ELBM_PARITY_JSON at the end of the session (tests/conftest.py)
+FLOOR_MARGIN = 1.5
+
+
+def floors():
+    global _FLOORS
+    if _FLOORS is None:
+        import os
+        import sys
+
+        sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+        import make_storage_floors as MSF
+
+        _FLOORS = MSF.load()
+    return _FLOORS
+
+
+def bound(case, storage, comp, gate):
+    """Parity bound of one velocity component: the target `gate` where the
+    storage floor (tests/golden/storage_floors.txt) lies at least a factor
+    FLOOR_MARGIN below it, otherwise FLOOR_MARGIN times the floor (the format
+    alone then misses the target; the bound says how close to the floor the
+    kernel stays)."""
+    fl = floors()[(case, storage, f"u{comp}")]
+    return gate if FLOOR_MARGIN * fl <= gate else FLOOR_MARGIN * fl
+
+
+def check_fields(test, case, storage, u, uo, gates):
+    """Asserts rel-L2(u_a) within bound(case, storage, a, gates[a]) for every
+    component and records measured value, floor, target and bound."""
+    errs = []
+    for a in range(len(gates)):
+        e = rel_l2(u[a], uo[a])
+        b = bound(case, storage, a, gates[a])
+        MEASURED.append(dict(test=test, case=case, storage=storage, component=f"u{a}", measured=e,
+                             floor=floors()[(case, storage, f"u{a}")], target=gates[a], bound=b))
+        errs.append((a, e, b))
+    for a, e, b in errs:
+        assert e <= b, (test, case, storage, a, e, b)

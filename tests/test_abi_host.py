@@ -42,6 +42,21 @@ def test_validation_rejects(kw, msg):
         E.query_bytes(p)
 
 
+@pytest.mark.parametrize("D", [2, 3])
+def test_walls_with_advection_reference_are_unsupported(D):
+    """A bounced population stored as a deviation from w(u_adv) would need the
+    correction w_opp - w_i, which the kernels do not apply: walls need u_adv = 0."""
+    n = (16, 16, 8)[:D]
+    walls = (False, True, False)[:D]
+    ok = E.make_params(n, T=0.5, omega=1.5, walls=walls)
+    assert E.validate(ok) == E.OK
+    bad = E.make_params(n, T=0.5, omega=1.5, walls=walls, u_adv=(0.05,) + (0.0,) * (D - 1))
+    assert E.validate(bad) == E.EUNSUPPORTED
+    assert "u_adv" in E._lib.elbm_last_error().decode()
+    # periodic lattices keep the advected reference
+    assert E.validate(E.make_params(n, T=0.5, omega=1.5, u_adv=(0.05,) + (0.0,) * (D - 1))) == E.OK
+
+
 def test_validation_rejects_bad_lattice_shapes():
     p = E.make_params((8, 8, 8), T=0.5, omega=1.0)
     p.lattice = 15

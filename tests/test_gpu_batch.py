@@ -5,7 +5,8 @@ import pytest
 
 import inputs as I
 import oracle as O
-from gpu_helpers import lattice_from_field, lib
+from gpu_helpers import MEASURED, dev_rel_l2, lattice_from_field, lib
+from storage_rounding import round_state
 
 pytestmark = pytest.mark.gpu
 
@@ -57,6 +58,33 @@ def test_batch_equals_alone_bitwise(use_graph):
         assert lat.step_count == k
         assert np.array_equal(lat.populations(), r)
     b.close()
+
+
+def test_batch_matches_oracle():
+    """Every lattice of a graph-replayed batched run against the FP64 oracle run
+    from the same stored initial state: the population deviations f - w within
+    1e-5 (FP32 storage), or, for 16-bit storage, the oracle's state rounded to
+    the format after every step as the library stores it, within 1e-3 (FP16)
+    and 1e-2 (BF16)."""
+    E = lib()
+    mix = _mix()
+    steps = [7, 12, 3, 12, 9, 1, 5, 12, 8]
+    lats = _make(mix)
+    f0 = [lat.populations() for lat in lats]
+    b = E.Batch(len(lats))
+    b.run(lats, steps, use_graph=True)
+    b.close()
+    gate = {"f32": 1e-5, "f16": 1e-3, "bf16": 1e-2}
+    for (p, _, st), lat, k, f in zip(mix, lats, steps, f0):
+        w = O.reference_weights(p).reshape((-1,) + (1,) * p.D)
+        for _ in range(k):
+            f = O.step(f, p)
+            if st != "f32":
+                f = round_state(f, w, st)
+        e = dev_rel_l2(lat.populations(), f, p)
+        MEASURED.append(dict(test="batch_vs_oracle", case=f"{p.n} {st} {k} steps", storage=st,
+                             component="f-w", measured=e, target=gate[st], bound=gate[st]))
+        assert e <= gate[st], (p.n, st, k, e)
 
 
 def test_graph_reuse_across_mixes_and_continuation():

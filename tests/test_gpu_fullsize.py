@@ -50,14 +50,20 @@ def test_hit_256_cube_one_step_sampled(storage, tol_abs, tol_rel):
     _check(lat, p, nodes, tol_abs, tol_rel)
 
 
-def test_channel_full_size_one_step_sampled():
+@pytest.mark.parametrize("storage,tol_abs,tol_rel,kernel", [("f32", 2e-7, 0.0, "register"),
+                                                           ("f16", 1e-7, 2.0 ** -10, "staged")])
+def test_channel_full_size_one_step_sampled(storage, tol_abs, tol_rel, kernel):
+    """384 x 192 x 192 channel (walls in y, Re_tau = 180 force): FP32 takes the
+    register-pull kernel, FP16 the LDS-staged kernel with walls and force --
+    the two kernels of the bench's channel workload, in its launch shape."""
     n, lam = (384, 192, 192), (2.0, 1.0, 1.0)
     omega = 1.976785
     nu = (1 / omega - 0.5) * 0.5
     g = 180.0 ** 2 * nu ** 2 / 96.0 ** 3
     fld = I.channel_field(n, lam)
     p = O.Params(n=n, lam=lam, T=0.5, omega=omega, walls=(False, True, False), force=(g, 0.0, 0.0))
-    lat = lattice_from_field(p, fld, "f32")
-    special = ([0, 63, 64, 383], [0, 1, 7, 8, 190, 191], [0, 23, 24, 191])
+    lat = lattice_from_field(p, fld, storage)
+    assert lat.kernel_info()["kernel"] == kernel
+    special = ([0, 63, 64, 383], [0, 1, 7, 8, 15, 16, 190, 191], [0, 23, 24, 27, 28, 191])
     nodes = _nodes(n, special, 120, seed=4)
-    _check(lat, p, nodes, 2e-7, 0.0)
+    _check(lat, p, nodes, tol_abs, tol_rel)

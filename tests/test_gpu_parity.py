@@ -5,21 +5,17 @@ Tolerances (FP32 arithmetic on deviations, FP64 oracle):
 * one step from an arbitrary state: max |f_gpu - f_oracle| <= 2e-7 and the
   rel-L2 of the deviations f - w <= 2e-6;
 * ten steps: rel-L2 of the deviations <= 1e-5;
-* workload fields after 100 steps: rel-L2 of every non-uniform velocity
-  component <= 1e-5 with FP32 storage, <= 1e-3 with FP16 deviation storage;
-  BF16 storage (8 significand bits) is held to <= 1e-2.
-
-Where a velocity component is a small perturbation of a large mean flow the
-rounding floor is set by the mean flow, not by the component: each step adds
-about eps |h| of error per population, |h| ~ U/2 the deviation carried by the
-mean flow U, while the component's own size is delta U. Those cases state
-their bound as eps-scaled from this estimate:
-* double shear layer (omega = 1.973, relaxation barely damps the error):
-  FP32 eps |h| ~ 3e-9 per step, ~5e-8 after 100 steps against u_y rms 3.5e-3
-  -> rel-L2(u_y) ~ 1.5e-5, bound 4e-5;
-* channel with FP16 storage: eps_16 |h| ~ 7e-6 against a transverse
-  perturbation rms ~ 4e-4 -> rel-L2(u_y, u_z) ~ 2e-3, bound 5e-3 (the mean
-  flow component keeps the 1e-3 bound).
+* workload fields after 100 steps: rel-L2 of every velocity component
+  <= 1e-5 with FP32 storage, <= 1e-3 with FP16 deviation storage and
+  <= 1e-2 with BF16 (8 significand bits) -- unless the storage format alone
+  causes more: tests/golden/storage_floors.txt holds, per case, format and
+  component, the error of the FP64 oracle whose state is rounded to the
+  format after every step. Where that floor times 1.5 exceeds the target,
+  the bound is 1.5 times the floor (gpu_helpers.bound): the FP16 channel's
+  transverse components (floors 2.3e-3 and 3.6e-3 at 96 x 48 x 48: a
+  perturbation of rms 4e-3 riding on a mean flow of 0.075 whose deviations
+  the 11-bit format rounds) and the BF16 channel. Every measured error is
+  recorded with its floor, target and bound ($ELBM_PARITY_JSON).
 """
 import math
 
@@ -28,7 +24,8 @@ import pytest
 
 import inputs as I
 import oracle as O
-from gpu_helpers import dev_rel_l2, lattice_from_field, lib, oracle_init, params_for, random_state, rel_l2
+from gpu_helpers import (MEASURED, check_fields, dev_rel_l2, lattice_from_field, lib, oracle_init, params_for,
+                         random_state, rel_l2)
 
 pytestmark = pytest.mark.gpu
 
@@ -96,7 +93,7 @@ def test_init_matches_equilibrium(storage):
 
 
 def _cfg1(T, storage, via_uadv):
-    """Returns rel-L2(u_y), rel-L2(u_x) and max |u_x - U0| after 100 steps."""
+    """GPU and oracle velocities after 100 steps, and the floor-table case name."""
     fld = I.shear_wave_axis((64, 64), U0=0.0 if via_uadv else 0.1, A=0.01)
     uadv = (0.1, 0.0) if via_uadv else None
     p = O.Params(n=(64, 64), T=T, omega=1.8)
@@ -106,32 +103,33 @@ def _cfg1(T, storage, via_uadv):
     fo = O.run(fo, p, 100)
     rho, u = lat.fields()
     _, uo = O.velocity(fo, p)
-    return rel_l2(u[1], uo[1]), rel_l2(u[0], uo[0]), np.abs(u[0] - 0.1).max()
+    case = f"cfg1_T{0.5 if T == 0.5 else 0.33}_{'uadv' if via_uadv else 'rest'}"
+    return u, uo, case
 
 
 @pytest.mark.parametrize("T", [1 / 3, 0.5])
 @pytest.mark.parametrize("via_uadv", [True, False])
 def test_cfg1_shear_wave_fp32(T, via_uadv):
-    """D2Q9 64x64, U0 = 0.1, A = 0.01, omega = 1.8, 100 steps: rel-L2(u_y) <= 1e-5."""
-    e, ex, ux = _cfg1(T, "f32", via_uadv)
-    assert e <= 1e-5
-    assert ex <= 1e-5
-    # u_x stays U0 in exact arithmetic (dormant anomaly); with u_ref = 0 the
-    # stored deviations carry U0 itself and round at eps * 0.03
-    assert ux <= (1e-6 if via_uadv else 3e-6)
+    """D2Q9 64x64, U0 = 0.1, A = 0.01, omega = 1.8, 100 steps: rel-L2 of u_x and
+    u_y <= 1e-5, and u_x = U0 (dormant anomaly: exact in exact arithmetic) to 1e-6."""
+    u, uo, case = _cfg1(T, "f32", via_uadv)
+    check_fields("cfg1", case, "f32", u, uo, (1e-5, 1e-5))
+    ux = np.abs(u[0] - 0.1).max()
+    MEASURED.append(dict(test="cfg1", case=case, storage="f32", component="ux_dev", measured=float(ux), target=1e-6,
+                         bound=1e-6))
+    assert ux <= 1e-6
 
 
 @pytest.mark.parametrize("T", [1 / 3, 0.5])
 def test_cfg1_shear_wave_fp16(T):
-    e, ex, ux = _cfg1(T, "f16", True)
-    assert e <= 1e-3
-    assert ex <= 1e-3
-    assert ux <= 1e-4
+    u, uo, case = _cfg1(T, "f16", True)
+    check_fields("cfg1", case, "f16", u, uo, (1e-3, 1e-3))
+    assert np.abs(u[0] - 0.1).max() <= 1e-4
 
 
 def test_cfg1_shear_wave_bf16():
-    e, _, _ = _cfg1(1 / 3, "bf16", True)
-    assert e <= 1e-2
+    u, uo, case = _cfg1(1 / 3, "bf16", True)
+    check_fields("cfg1", case, "bf16", u, uo, (1e-2, 1e-2))
 
 
 _hit_cache = {}
@@ -154,16 +152,17 @@ def test_hit_64_cube(storage, tol):
     lat.step(100)
     _, u = lat.fields()
     _, uo = O.velocity(fo, p)
-    for a in range(3):
-        assert rel_l2(u[a], uo[a]) <= tol, (storage, a)
+    check_fields("hit", "hit64", storage, u, uo, (tol, tol, tol))
 
 
 _chan_cache = {}
 
 
-def _channel():
-    if "fo" not in _chan_cache:
-        n, lam = (96, 48, 48), (2.0, 1.0, 1.0)
+def _channel(n=(96, 48, 48)):
+    """Sec. 3.5 channel (lambda = (2, 1, 1), walls in y, Re_tau = 180 force) and
+    its oracle state after 100 steps."""
+    if n not in _chan_cache:
+        lam = (2.0, 1.0, 1.0)
         H = 0.5 * n[1] * lam[1]
         omega = 1.976785
         nu = (1 / omega - 0.5) * 0.5
@@ -171,33 +170,51 @@ def _channel():
         fld = I.channel_field(n, lam)
         p = O.Params(n=n, lam=lam, T=0.5, omega=omega, walls=(False, True, False), force=(g, 0.0, 0.0))
         fo = O.run(oracle_init(p, fld), p, 100)
-        _chan_cache.update(fld=fld, p=p, fo=fo)
-    return _chan_cache["fld"], _chan_cache["p"], _chan_cache["fo"]
+        _chan_cache[n] = (fld, p, fo)
+    return _chan_cache[n]
 
 
-@pytest.mark.parametrize("storage,tols", [("f32", (1e-5, 1e-5, 1e-5)), ("f16", (1e-3, 5e-3, 5e-3))])
-def test_channel_stretched_walls_force(storage, tols):
-    """D3Q27 lam = (2,1,1), bounce-back in y, body force, 96x48x48, 100 steps."""
+@pytest.mark.parametrize("storage,gate", [("f32", 1e-5), ("f16", 1e-3), ("bf16", 1e-2)])
+def test_channel_stretched_walls_force(storage, gate):
+    """D3Q27 lam = (2,1,1), bounce-back in y, body force, 96x48x48, 100 steps
+    (n_x % 64 != 0: the register-pull kernel for every storage)."""
     fld, p, fo = _channel()
     lat = lattice_from_field(p, fld, storage)
+    assert lat.kernel_info()["kernel"] == "register"
     lat.step(100)
     _, u = lat.fields()
     _, uo = O.velocity(fo, p)
-    for a in range(3):
-        assert rel_l2(u[a], uo[a]) <= tols[a], (storage, a)
+    check_fields("channel", "channel96", storage, u, uo, (gate, gate, gate))
 
 
-def test_double_shear_layer_256():
-    """D2Q9 double shear layer (Re = 30000 scaled to L = 256 at constant nu), 100 steps."""
+@pytest.mark.parametrize("storage,gate", [("f32", 1e-5), ("f16", 1e-3), ("bf16", 1e-2)])
+def test_channel_staged_size_100_steps(storage, gate):
+    """The same channel at 128 x 48 x 32 (n_x % 64 == 0, n_y % 16 == 0): FP16 and
+    BF16 take the LDS-staged kernel with y walls and force, the kernel of the
+    full-size channel, for 100 steps against the oracle."""
+    fld, p, fo = _channel((128, 48, 32))
+    lat = lattice_from_field(p, fld, storage)
+    assert lat.kernel_info()["kernel"] == ("register" if storage == "f32" else "staged")
+    lat.step(100)
+    _, u = lat.fields()
+    _, uo = O.velocity(fo, p)
+    check_fields("channel_staged", "channel128x48x32", storage, u, uo, (gate, gate, gate))
+
+
+@pytest.mark.parametrize("storage,gate", [("f32", 1e-5), ("f16", 1e-3)])
+def test_double_shear_layer_256(storage, gate):
+    """D2Q9 double shear layer (Re = 30000 scaled to L = 256 at constant nu,
+    omega = 1.973), 100 steps. FP16's floor on u_y (1.1e-2: the layer's
+    transverse perturbation is 5% of the stream speed the deviations carry)
+    sets its bound."""
     fld = I.double_shear_layer((256, 256))
     p = O.Params(n=(256, 256), T=0.5, omega=1.973061)
-    lat = lattice_from_field(p, fld)
+    lat = lattice_from_field(p, fld, storage)
     lat.step(100)
     fo = O.run(oracle_init(p, fld), p, 100)
     _, u = lat.fields()
     _, uo = O.velocity(fo, p)
-    assert rel_l2(u[0], uo[0]) <= 1e-5
-    assert rel_l2(u[1], uo[1]) <= 4e-5
+    check_fields("dsl", "dsl256", storage, u, uo, (gate, gate))
 
 
 def test_diagnostics_match_oracle():
@@ -257,8 +274,20 @@ def _gpu_viscosity(n, lam, T, U0, storage, extended=True, steps=500, every=5, a0
 @pytest.mark.parametrize("T", [1 / 3, 0.5])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_viscosity_cfg1_on_gpu(T, storage):
-    """Sec. 3.1: fitted decay of the axis-aligned wave gives nu = (1/omega - 1/2) T within 1%."""
+    """Sec. 3.1: fitted decay of the axis-aligned wave gives nu = (1/omega - 1/2) T
+    within 1%, over the workload's 500 steps. With FP16 storage the fit is
+    only resolved to about 1%: the viscous decrement per step (nu k^2 = 1.8e-4
+    of the amplitude at T = 1/3) is 0.37 of FP16's unit roundoff, and the
+    fitted rate depends on the exact rounding sequence. The oracle with its
+    state rounded to FP16 after every step fits 0.9933 (T = 1/3) and 1.0073
+    (T = 1/2) (tests/golden/storage_floors.txt); float32 models of the
+    kernel's arithmetic with different operation orders land between 0.997
+    and 1.010 at T = 1/3, and the FP32-storage variant of the collision
+    (relaxation of the non-equilibrium part) ran at 1.0125 on the GPU. The
+    16-bit kernels therefore keep the plain relaxation order."""
     r = _gpu_viscosity((64, 64), (1.0, 1.0), T, 0.1, storage, rotated=False, a0=0.01)
+    MEASURED.append(dict(test="viscosity_cfg1", case=f"T={T:.3f} 500 steps", storage=storage,
+                         component="nu_fit/nu", measured=float(r - 1), target=1e-2, bound=1e-2))
     assert abs(r - 1) < 1e-2
 
 
@@ -362,3 +391,61 @@ def test_short_chunks_match_oracle(chunk, monkeypatch):
     assert np.abs(lat.populations() - o1).max() <= 2e-7
     lat.step(9)
     assert dev_rel_l2(lat.populations(), O.run(o1, p, 9), p) <= 1e-5
+
+
+@pytest.mark.parametrize("D,storage,n", [(2, "f32", (64, 8)), (3, "f32", (40, 8, 6))])
+def test_poiseuille_exact_at_magic_relaxation_on_gpu(D, storage, n):
+    """The GPU's walls, force and reported velocity (j + rho g/2)/rho against the
+    Navier-Stokes parabola u = g/(2 nu) y (2H - y), which LBGK with halfway
+    bounce-back reproduces without wall slip at tau = 1/2 + sqrt(3)/4 (the
+    oracle meets it to 1e-10). Without the half-force shift the profile would
+    be off by g/2 everywhere: 0.9% of the centreline value at 8 rows. FP32
+    storage, within 1e-5 of the centreline value. (FP16 storage cannot resolve
+    this steady state: at 64 x 16 x 4 the staged kernel's profile sits 3e-3
+    off, more than the g/2 shift, from rounding the small deviations of a
+    low-speed flow to 11 bits; the staged kernel's walls and force are checked
+    against the oracle over 100 steps instead.)"""
+    tau = 0.5 + math.sqrt(3.0) / 4.0
+    g = 1e-5
+    ny = n[1]
+    walls = (False, True) + ((False,) if D == 3 else ())
+    p = O.Params(n=n, T=1.0 / 3.0, omega=1.0 / tau, walls=walls, force=(g,) + (0.0,) * (D - 1))
+    grid = tuple(reversed(n))
+    y = np.arange(ny) + 0.5
+    exact = g / (2.0 * p.nu) * y * (ny - y)
+    u0 = np.zeros((D,) + grid)
+    shape = [1] * D
+    shape[D - 2] = ny
+    u0[0] = exact.reshape(shape)
+    fld = I.Field(np.ones(grid), u0, n, (1.0,) * D)
+    lat = lattice_from_field(p, fld, storage)
+    lat.step(1500)
+    _, u = lat.fields()
+    ux = np.moveaxis(u[0], D - 2, 0).reshape(ny, -1)
+    err = np.abs(ux - exact[:, None]).max() / exact.max()
+    tol = 1e-5
+    MEASURED.append(dict(test="poiseuille_magic_tau", case=f"D{D} {n}", storage=storage, component="u0",
+                         measured=float(err), target=tol, bound=tol))
+    assert err <= tol
+    assert 0.5 * g / exact.max() > 2 * tol  # the unshifted velocity would fail
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_enstrophy_3d_closed_form_on_gpu(walls):
+    """GPU enstrophy of a state initialised with a velocity field whose
+    central-difference curl is known node by node (all three components
+    nonzero, unequal spacings; with walls, the no-slip ghost on y): against the
+    closed form directly, not only against the oracle."""
+    import importlib
+    import sys as _sys
+
+    _sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    tod = importlib.import_module("test_oracle_dynamics")
+    p, u, exact = tod._vorticity_closed_form_case(walls)
+    fld = I.Field(np.ones(u.shape[1:]), u, p.n, p.lam)
+    lat = lattice_from_field(p, fld, "f32")
+    d = lat.diag()
+    e = abs(d["enstrophy"] / exact.mean() - 1)
+    MEASURED.append(dict(test="enstrophy_closed_form", case=f"walls={walls}", storage="f32", component="enstrophy",
+                         measured=float(e), target=1e-5, bound=1e-5))
+    assert e <= 1e-5
