@@ -267,6 +267,29 @@ int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps
                        int32_t count, int32_t use_graph);
 int32_t elbm_batch_destroy(elbm_batch b);
 
+/* ---- the same batched run for callers that cannot allocate ----
+ *
+ * For callers that must not allocate device or pinned host memory: code that
+ * runs between allocation-free phases of a serving loop, harnesses that forbid
+ * hipMalloc, streams being captured into a graph by the caller. Advances
+ * lattice hs[k] by steps[k] >= 0 steps exactly as elbm_batch_run (same
+ * kernels, same results bitwise), with no batch object: the per-class
+ * descriptor tables live in a fixed device array that the library holds on
+ * every device it runs on until the process ends (1024 + 304 *
+ * ELBM_STATIC_MAX_LATTICES bytes); they are written by small kernels whose
+ * arguments carry the bytes. Nothing is allocated and no graph is captured.
+ *  hs, steps   count lattices (all on the current device, none twice) and
+ *              their step counts; count <= ELBM_STATIC_MAX_LATTICES, else
+ *              ELBM_EINVAL.
+ *  hip_stream  the stream the run is queued on (may be NULL); it first waits
+ *              for the work queued on the lattices' streams, and they wait
+ *              for the run's end.
+ * Every call on a device rewrites the one table array of that device: calls
+ * whose runs overlap on one device (different streams, no ordering between
+ * them) race and must not be made. Automatic diagnostics are not recorded. */
+#define ELBM_STATIC_MAX_LATTICES 256
+int32_t elbm_batch_run_static(const elbm_handle* hs, const int64_t* steps, int32_t count, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libelbm.so")
 
-SOURCES = ["elbm_step.hip", "elbm_aux.hip", "elbm_api.cpp"]
+SOURCES = ["elbm_step.hip", "elbm_aux.hip", "elbm_static.hip", "elbm_api.cpp"]
 ARCH = "gfx950"
 
 

@@ -84,6 +84,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int class_of(int D, int storage, bool wall, bool force, bool staged) {
   return ((((D == 3) * 3 + storage) * 2 + (wall ? 1 : 0)) * 2 + (force ? 1 : 0)) * 2 + (staged ? 1 : 0);
 }
+static_assert(kClasses == kStaticClasses, "one static table per kernel class");
 
 // The kernel class of index c (inverse of class_of).
 struct ClassKey {
@@ -858,6 +859,94 @@ int32_t elbm_batch_destroy(elbm_batch b) {
   (void)hipEventDestroy(b->entry);
   (void)hipStreamDestroy(b->stream);
   delete b;
+  return ELBM_OK;
+}
+
+// ------------------------------------------- allocation-free batched runs
+
+int32_t elbm_batch_run_static(const elbm_handle* hs, const int64_t* steps, int32_t count, void* hip_stream) {
+  if (count < 0 || count > kStaticMaxLattices)
+    return fail(ELBM_EINVAL, "elbm_batch_run_static takes at most " + std::to_string(kStaticMaxLattices) +
+                                 " lattices per call (" + std::to_string(count) + " given)");
+  if (count == 0) return ELBM_OK;
+  if (!hs || !steps) return fail(ELBM_EINVAL, "NULL argument");
+  for (int32_t k = 0; k < count; ++k) {
+    if (!hs[k]) return fail(ELBM_EINVAL, "NULL handle in batch");
+    if (steps[k] < 0) return fail(ELBM_EINVAL, "steps must be >= 0");
+    if (hs[k]->device != hs[0]->device) return fail(ELBM_EINVAL, "lattices on different devices");
+    for (int32_t m = 0; m < k; ++m)
+      if (hs[m] == hs[k]) return fail(ELBM_EINVAL, "a lattice appears twice in the batch");
+  }
+  int32_t s = set_dev(hs[0]->device);
+  if (s) return s;
+  int64_t smax = 0;
+  for (int32_t k = 0; k < count; ++k) smax = std::max(smax, steps[k]);
+  if (smax == 0) return ELBM_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  void* scr = nullptr;
+  HIPCHK(static_scratch(&scr));  // first call on this device: looks the address up
+
+  // Table image (host, fixed size): class headers, then the descriptors of
+  // every class in class order, each class in the caller's order.
+  thread_local unsigned char image[kStaticScratchBytes];
+  auto* hdrs = reinterpret_cast<TableHeader*>(image);
+  auto* descs = reinterpret_cast<LatticeDesc*>(image + kStaticHeaderBytes);
+  int32_t first[kClasses], ncls[kClasses];
+  int64_t tiles[kClasses];
+  int32_t order[kStaticMaxLattices];
+  for (int c = 0; c < kClasses; ++c) ncls[c] = 0, tiles[c] = 0;
+  for (int32_t k = 0; k < count; ++k)
+    if (steps[k] > 0) {
+      const elbm_lattice* h = hs[k];
+      ++ncls[class_of(h->D, h->p.storage, h->wall, h->force, h->staged)];
+    }
+  int32_t used = 0;
+  for (int c = 0; c < kClasses; ++c) {
+    first[c] = used;
+    used += ncls[c];
+    ncls[c] = 0;
+  }
+  for (int32_t k = 0; k < count; ++k) {
+    if (steps[k] == 0) continue;
+    const elbm_lattice* h = hs[k];
+    const int c = class_of(h->D, h->p.storage, h->wall, h->force, h->staged);
+    order[first[c] + ncls[c]++] = k;
+  }
+  for (int c = 0; c < kClasses; ++c) {
+    for (int32_t m = 0; m < ncls[c]; ++m) {
+      const int32_t k = order[first[c] + m];
+      LatticeDesc d = hs[k]->desc;
+      d.tile_base = tiles[c];
+      d.parity0 = int32_t(hs[k]->step & 1);
+      d.nsteps = steps[k];
+      tiles[c] += d.ntiles;
+      descs[first[c] + m] = d;
+    }
+    hdrs[c] = TableHeader{ncls[c], 0, tiles[c]};
+  }
+  const size_t bytes = kStaticHeaderBytes + size_t(used) * sizeof(LatticeDesc);
+
+  // order after the work queued on the lattices' streams
+  for (int32_t k = 0; k < count; ++k) {
+    HIPCHK(hipEventRecord(hs[k]->event, hs[k]->stream));
+    HIPCHK(hipStreamWaitEvent(st, hs[k]->event, 0));
+  }
+  HIPCHK(launch_write_bytes(scr, image, bytes, st));
+  auto* dhdr = static_cast<const TableHeader*>(scr);
+  auto* dtab = reinterpret_cast<const LatticeDesc*>(static_cast<const unsigned char*>(scr) + kStaticHeaderBytes);
+  for (int64_t sub = 0; sub < smax; ++sub)
+    for (int c = 0; c < kClasses; ++c) {
+      if (ncls[c] == 0) continue;
+      const ClassKey ck = class_key(c);
+      HIPCHK(launch_step(ck.D, ck.storage, ck.wall, ck.force, ck.staged, dhdr + c, dtab + first[c], sub,
+                         batch_grid(tiles[c]), st));
+    }
+  // the lattices' streams wait for the run
+  for (int32_t k = 0; k < count; ++k) {
+    hs[k]->step += steps[k];
+    HIPCHK(hipEventRecord(hs[k]->event, st));
+    HIPCHK(hipStreamWaitEvent(hs[k]->stream, hs[k]->event, 0));
+  }
   return ELBM_OK;
 }
 

@@ -108,6 +108,20 @@ struct LatticeConst64 {
   int32_t has_mode;
 };
 
+// ---- allocation-free batched runner (elbm_static.hip) ----
+constexpr int kStaticMaxLattices = 256;   // lattices per elbm_batch_run_static call
+constexpr int kStaticClasses = 48;        // kernel classes (one table each)
+constexpr size_t kStaticHeaderBytes = 1024;  // kStaticClasses TableHeaders, padded
+constexpr size_t kStaticScratchBytes = kStaticHeaderBytes + size_t(kStaticMaxLattices) * sizeof(LatticeDesc);
+static_assert(kStaticClasses * sizeof(TableHeader) <= kStaticHeaderBytes, "table headers fit");
+static_assert(kStaticHeaderBytes % alignof(LatticeDesc) == 0, "descriptors stay aligned");
+// Device address of the fixed scratch array on the current device (looked up
+// once per device and kept).
+hipError_t static_scratch(void** out);
+// Writes `bytes` host bytes to device memory `dst` with kernels on `st` (the
+// bytes travel as kernel arguments: no staging memory).
+hipError_t launch_write_bytes(void* dst, const unsigned char* src, size_t bytes, hipStream_t st);
+
 // ---- launchers (defined in the .hip translation units) ----
 // staged: the LDS-staged D3Q27 kernel for 16-bit storage (periodic, full tiles).
 hipError_t launch_step(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,

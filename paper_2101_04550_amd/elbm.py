@@ -113,7 +113,9 @@ _sigs = {
     "elbm_batch_create": (C.c_int32, [C.c_int32, C.c_void_p, _P(C.c_void_p)]),
     "elbm_batch_run": (C.c_int32, [C.c_void_p, _P(C.c_void_p), _P(C.c_int64), C.c_int32, C.c_int32]),
     "elbm_batch_destroy": (C.c_int32, [C.c_void_p]),
+    "elbm_batch_run_static": (C.c_int32, [_P(C.c_void_p), _P(C.c_int64), C.c_int32, C.c_void_p]),
 }
+STATIC_MAX_LATTICES = 256
 for _name, (_res, _args) in _sigs.items():
     _fn = getattr(_lib, _name)
     _fn.restype = _res
@@ -333,3 +335,15 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def batch_run_static(lattices, steps, stream=None):
+    """elbm_batch_run_static: the batched run with the library's fixed device
+    tables (no allocation); `stream` defaults to torch's current stream."""
+    import torch
+
+    st = stream if stream is not None else torch.cuda.current_stream()
+    count = len(lattices)
+    hs = (C.c_void_p * max(count, 1))(*[lat.handle for lat in lattices])
+    ks = (C.c_int64 * max(count, 1))(*[int(k) for k in steps])
+    _check(_lib.elbm_batch_run_static(hs, ks, count, C.c_void_p(st.cuda_stream)), "elbm_batch_run_static")
