@@ -9,9 +9,12 @@ energy / enstrophy reductions run every 50 steps inside the timed region,
 as in the workload. Inputs are resident in HBM before timing starts.
 
 Prints one JSON line: MLUPS (FP32 deviation storage) as `value`, the FP16 and
-BF16 deviation-storage runs of the same workload beside it, the roofline of
-the step kernel (algorithmic bytes 2 Q s per node, measured with HIP events on
-the launch stream), and the FP64 CPU oracle timed on a bounded sample.
+BF16 deviation-storage runs of the same workload beside it (whole-job and
+kernel-time ratios), the roofline of the step kernel (algorithmic bytes 2 Q s
+per node, measured with HIP events on the launch stream) with the achievable
+ceiling measured by the bandwidth probe, the channel and D2Q9 workloads, the
+served mixed stream at its own rate (saturated) and at half of it (under
+capacity), and the FP64 CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -62,6 +65,9 @@ def parse_args():
                     help="requests of the served mixed stream (0: skip the serving leg)")
     ap.add_argument("--channel-only", action="store_true",
                     help="only the 384x192x192 channel leg (FP32 and FP16), one JSON line: for per-kernel profiles")
+    ap.add_argument("--no-ceiling", action="store_true", help="omit the bandwidth-ceiling probe")
+    ap.add_argument("--ceiling-only", action="store_true",
+                    help="only the bandwidth-ceiling probe, one JSON line: for its kernel profile")
     ap.add_argument("--hit-only", action="store_true",
                     help="only the 256^3 turbulence legs (no D2Q9 or serving leg): for per-kernel profiles")
     return ap.parse_args()
@@ -111,15 +117,34 @@ def run_gpu(storage, fld, steps, warmup, kernel_reps):
 
     n = fld.n
     N = math.prod(n)
+    # Both lattices are set up first, so that no host work (initial fields,
+    # uploads) separates the two timed parts: the GPU's clocks drop within a
+    # fraction of a second of idling and take ~30-60 launches (~20 ms) to come
+    # back, which would put a short whole-job window into the ramp (the
+    # 16-bit kernels, more arithmetic-bound, run 5-9% slower during it).
+    p2 = E.make_params(n, T=T_HIT, omega=OMEGA_HIT, storage=storage)
+    kl = E.Lattice(p2)
+    kl.init(fld.rho, fld.u)
     params = E.make_params(n, T=T_HIT, omega=OMEGA_HIT, storage=storage, diag_every=DIAG_EVERY,
                            diag_capacity=max(1, (steps + warmup) // DIAG_EVERY + 1))
     lat = E.Lattice(params)
     lat.init(fld.rho, fld.u)
     info = lat.kernel_info()
     stream = lat.stream
+    # step-kernel duration: diagnostics off, events on the launch stream around
+    # kernel_reps back-to-back step launches, after 60 untimed ones (past the
+    # clock ramp that follows the set-up)
+    kl.step(60)
+    kl.sync()
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    k0.record(kl.stream)
+    kl.step(kernel_reps)
+    k1.record(kl.stream)
+    # whole-job timed region: W warm-up steps, then exactly K steps (with the
+    # FP64 diagnostics of every 50th step), bracketed by synchronisations
     lat.step(warmup)
     lat.sync()
-    # whole-job timed region: K steps incl. the FP64 diagnostics every 50 steps
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -129,24 +154,12 @@ def run_gpu(storage, fld, steps, warmup, kernel_reps):
     t1.synchronize()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
-    hist = lat.diag_history()
-    lat.close()
-    del lat
-    # step-kernel duration: same lattice shape, diagnostics off, events on the
-    # launch stream around kernel_reps back-to-back step launches
-    p2 = E.make_params(n, T=T_HIT, omega=OMEGA_HIT, storage=storage)
-    lat = E.Lattice(p2)
-    lat.init(fld.rho, fld.u)
-    lat.step(5)
-    lat.sync()
-    k0 = torch.cuda.Event(enable_timing=True)
-    k1 = torch.cuda.Event(enable_timing=True)
-    k0.record(lat.stream)
-    lat.step(kernel_reps)
-    k1.record(lat.stream)
-    k1.synchronize()
     kms = k0.elapsed_time(k1) / kernel_reps
-    d = lat.diag()
+    d = kl.diag()
+    kl.close()
+    del kl
+    hist = lat.diag_history()
+    timed = [h for h in hist if warmup < h["step"] <= warmup + steps]
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -159,6 +172,7 @@ def run_gpu(storage, fld, steps, warmup, kernel_reps):
         "kernel_ms": kms,
         "kernel_gbs": alg_bytes / (kms * 1e-3) / 1e9,
         "alg_bytes_per_launch": alg_bytes,
+        "diag_samples_timed": len(timed),
         "ke_first": hist[0]["ke"] if hist else None,
         "ke_last": hist[-1]["ke"] if hist else None,
         "enstrophy_last": hist[-1]["enstrophy"] if hist else None,
@@ -167,27 +181,95 @@ def run_gpu(storage, fld, steps, warmup, kernel_reps):
     }
 
 
-def serving_leg(nreq):
+def serving_leg(nreq, rate):
     """Continuous batching of the seeded mixed stream: Poisson arrivals at
-    50 req/s, 10% D3Q27 turbulence boxes (64^3..192^3), the rest D2Q9 shear
+    `rate` req/s, 10% D3Q27 turbulence boxes (64^3..192^3), the rest D2Q9 shear
     waves and double shear layers (64^2..1024^2), cubic or stretched, T in
-    {1/3, 1/2}, 200..5000 steps, FP32 / FP16 storage."""
+    {1/3, 1/2}, 200..5000 steps, FP32 / FP16 storage. Latency = completion -
+    arrival; offered_glups = the stream's node updates over its arrival
+    window (above the sustained rate the queue grows and latency measures the
+    backlog)."""
     import torch
 
     from paper_2101_04550_amd import serving as SV
 
-    reqs = SV.attach_fields(SV.make_stream(nreq, rate=50.0, share_3d=0.1))
+    reqs = SV.attach_fields(SV.make_stream(nreq, rate=rate, share_3d=0.1))
     window = reqs[-1].arrival
     offered = sum(r.cells * r.steps for r in reqs)
     srv = SV.Server(64 * 2 ** 30, max_slots=64, quantum=100, use_graph=True)
     res = srv.run(reqs)
     out = SV.summarize(res, srv.makespan)
-    out.update({"arrival_rate_per_s": 50.0, "share_3d": 0.1, "quantum_steps": 100, "rounds": srv.rounds,
+    out.update({"arrival_rate_per_s": rate, "share_3d": 0.1, "quantum_steps": 100, "rounds": srv.rounds,
                 "peak_slots": srv.peak_slots, "pool_gb": 64, "arrival_window_s": window,
                 "offered_glups": offered / window / 1e9})
     srv.close()
     torch.cuda.empty_cache()
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
+
+
+def ceiling_leg(n=N_HIT, reps=20):
+    """Achievable bandwidth of the step's access pattern on this device: the
+    population traffic of one D3Q27 step (27 pulled loads and 27 nontemporal
+    stores per node, plane slabs) without arithmetic (libelbm_probe.so), at
+    the step kernels' occupancies and at full occupancy, FP32 and FP16; and a
+    plain device copy (torch) of 2 GiB."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2101_04550_amd import elbm as E  # noqa: F401  (same HIP runtime as torch)
+
+    lib = C.CDLL(os.path.join(ROOT, "paper_2101_04550_amd", "libelbm_probe.so"))
+    lib.elbm_probe_bytes.argtypes = [C.c_int32] * 4 + [C.POINTER(C.c_size_t)]
+    lib.elbm_probe_stream.argtypes = [C.c_void_p, C.c_void_p] + [C.c_int32] * 8 + [C.c_void_p, C.POINTER(C.c_float)]
+    lib.elbm_probe_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_int32, C.c_int32,
+                                    C.c_void_p, C.POINTER(C.c_float)]
+    out = {}
+    st = torch.cuda.current_stream()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    plane_blocks = (n * n + 511) // 512
+    for es, name in ((4, "f32"), (2, "f16")):
+        nb = C.c_size_t(0)
+        assert lib.elbm_probe_bytes(es, n, n, n, C.byref(nb)) == 0
+        a = torch.zeros(nb.value, dtype=torch.uint8, device="cuda")
+        b = torch.zeros_like(a)
+        res = {}
+        # blocks of 512 threads per CU: 1 (the FP32 step kernel's 8 waves), 2
+        # (the FP16 staged kernel's 16 waves), 4 (full occupancy of the probe)
+        for bpc, lds in ((1, 96 * 1024), (2, 64 * 1024), (4, 0)):
+            chunk = max(1, n * plane_blocks // (cus * bpc))
+            ms = C.c_float(0)
+            rc = lib.elbm_probe_stream(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), es, n, n, n, chunk, 1,
+                                       lds, reps, C.c_void_p(st.cuda_stream), C.byref(ms))
+            assert rc == 0, rc
+            res[f"{bpc * 8}_waves_per_cu"] = round(2 * 27 * es * n ** 3 / (ms.value * 1e-3) / 1e9, 1)
+        out[name] = res
+        del a, b
+        torch.cuda.empty_cache()
+    x = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    res = {}
+    for per_cu in (2, 4, 8):
+        for unroll in (1, 2, 4):
+            ms = C.c_float(0)
+            rc = lib.elbm_probe_copy(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), x.numel() * 4,
+                                     cus * per_cu, unroll, reps, C.c_void_p(st.cuda_stream), C.byref(ms))
+            assert rc == 0, rc
+            res[f"{per_cu * 4}_waves_per_cu_x{unroll}"] = round(2 * x.numel() * 4 / (ms.value * 1e-3) / 1e9, 1)
+    out["copy16"] = res
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    out["torch_copy_gbs"] = round(2 * x.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del x, y
+    torch.cuda.empty_cache()
+    out["best_gbs"] = max([v for k in ("f32", "f16", "copy16") for v in out[k].values()] + [out["torch_copy_gbs"]])
+    out["unit"] = "GB/s (read + written)"
+    return out
 
 
 def d2q9_leg(n=1024, steps=2000):
@@ -269,8 +351,11 @@ def channel_leg(steps=300):
 
 def cpu_baseline(seconds_budget=20.0):
     """The FP64 NumPy oracle (untuned) on a bounded sample of the same workload:
-    a 96^3 box of the same spectrum (k0 = 4), timed over whole steps."""
+    a 96^3 box of the same spectrum (k0 = 4), timed over whole steps, on one
+    thread (the BLAS and OpenMP pools NumPy may use are capped to one thread
+    for the timed run)."""
     import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import inputs as I
     import oracle as O
@@ -279,15 +364,17 @@ def cpu_baseline(seconds_budget=20.0):
     fld = I.hit_field(n, k0=4.0, urms=0.05)
     p = O.Params(n=(n, n, n), T=T_HIT, omega=OMEGA_HIT)
     f = O.init_state(fld.rho, fld.u, p)
-    f = O.step(f, p)  # warm caches / allocator
-    steps = 0
-    t = time.perf_counter()
-    while True:
-        f = O.step(f, p)
-        steps += 1
-        if time.perf_counter() - t > seconds_budget or steps >= 200:
-            break
-    dt = time.perf_counter() - t
+    with threadpool_limits(limits=1):
+        pools = sorted({(pl["internal_api"], pl["num_threads"]) for pl in threadpool_info()})
+        f = O.step(f, p)  # warm caches / allocator
+        steps = 0
+        t = time.perf_counter()
+        while True:
+            f = O.step(f, p)
+            steps += 1
+            if time.perf_counter() - t > seconds_budget or steps >= 200:
+                break
+        dt = time.perf_counter() - t
     assert np.isfinite(f).all()
     cpu = platform.processor() or ""
     try:
@@ -304,6 +391,7 @@ def cpu_baseline(seconds_budget=20.0):
         "kind": "oracle",
         "sample": f"D3Q27 HIT {n}^3 (k0=4, T=0.5, omega={OMEGA_HIT}), {steps} FP64 NumPy steps in "
                   f"{dt:.1f} s on one core of {cpu} ({os.cpu_count()} logical CPUs visible)",
+        "thread_pools": [f"{api}:{k}" for api, k in pools],
     }
 
 
@@ -318,6 +406,9 @@ def main():
         return
     if args.channel_only:
         print(json.dumps({"channel": channel_leg()}), flush=True)
+        return
+    if args.ceiling_only:
+        print(json.dumps({"ceiling": ceiling_leg()}), flush=True)
         return
     import torch
 
@@ -349,7 +440,7 @@ def main():
         "config": {
             "workload": f"D3Q27 decaying HIT {args.n}^3 periodic, cubic lattice, T=0.5, omega={OMEGA_HIT}, "
                         f"u_rms=0.05, k0=4; {main_run['storage'].upper()} deviation storage; FP64 KE/enstrophy "
-                        f"every {DIAG_EVERY} steps",
+                        f"every {DIAG_EVERY} steps ({main_run['diag_samples_timed']} in the timed window)",
             "lattice": "D3Q27",
             "cells": N,
             "parallelism": "single GPU",
@@ -369,6 +460,9 @@ def main():
             s: {"mlups": round(r["mlups"], 1), "kernel_ms": round(r["kernel_ms"], 5),
                 "kernel_gbs": round(r["kernel_gbs"], 1),
                 "vs_f32": round(r["mlups"] / main_run["mlups"], 3),
+                "vs_f32_whole_job": round(r["mlups"] / main_run["mlups"], 3),
+                "vs_f32_kernel": round(main_run["kernel_ms"] / r["kernel_ms"], 3),
+                "diag_samples_timed": r["diag_samples_timed"],
                 "kernel": "step_kernel_lds (LDS staged)" if r["kernel"]["kernel"] == "staged"
                 else "step_kernel (register pull)",
                 "block_threads": r["kernel"]["block_threads"], "tile": list(r["kernel"]["tile"])}
@@ -381,10 +475,22 @@ def main():
     if args.n == N_HIT and not args.hit_only:
         out["d2q9"] = d2q9_leg()
         out["channel"] = channel_leg()
+    if args.n == N_HIT and not args.no_ceiling:
+        out["ceiling"] = ceiling_leg()
+        out["roofline"]["ceiling_gbs"] = out["ceiling"]["best_gbs"]
+        out["roofline"]["frac_of_ceiling"] = round(out["roofline"]["achieved"] / out["ceiling"]["best_gbs"], 4)
+        print(f"# ceiling: {out['ceiling']}", file=sys.stderr, flush=True)
     if args.serve_requests > 0 and args.n == N_HIT and not args.hit_only:
-        out["serving"] = serving_leg(args.serve_requests)
-        print(f"# serving: {out['serving']['solves_per_s']:.1f} solves/s, p50 {out['serving']['p50_latency_s']:.3f} s, "
-              f"p99 {out['serving']['p99_latency_s']:.3f} s", file=sys.stderr, flush=True)
+        # the stream's own rate (50 req/s: offered above what the GPU sustains,
+        # latency includes the backlog), then half of it (under capacity)
+        out["serving"] = {}
+        for rate in (50.0, 25.0):
+            out["serving"][f"rate_{int(rate)}"] = serving_leg(args.serve_requests, rate)
+        cap = out["serving"]["rate_50"]["sustained_glups"]
+        for key, sv in out["serving"].items():
+            sv["regime"] = "under capacity" if sv["offered_glups"] < 0.95 * cap else "saturated"
+            print(f"# serving {key} ({sv['regime']}): {sv['solves_per_s']:.1f} solves/s, "
+                  f"p50 {sv['p50_latency_s']:.3f} s, p99 {sv['p99_latency_s']:.3f} s", file=sys.stderr, flush=True)
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -1,4 +1,5 @@
-"""Builds libelbm.so (HIP kernels for gfx950 + the C ABI) in the package directory.
+"""Builds libelbm.so (HIP kernels for gfx950 + the C ABI) and the bandwidth
+probe libelbm_probe.so in the package directory.
 
 Usage: python -m paper_2101_04550_amd.build   (or build() from Python)
 
@@ -21,6 +22,9 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libelbm.so")
 
 SOURCES = ["elbm_step.hip", "elbm_aux.hip", "elbm_static.hip", "elbm_api.cpp"]
+# bandwidth probe of the step's access pattern (measurement only)
+PROBE_SOURCES = ["elbm_probe.hip"]
+PROBE_LIB = os.path.join(PKG, "libelbm_probe.so")
 ARCH = "gfx950"
 
 
@@ -55,18 +59,25 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, out, verbose):
+    tmp = out + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Builds libelbm.so and the bandwidth probe libelbm_probe.so."""
+    os.makedirs(BUILD, exist_ok=True)
+    sources = SOURCES + PROBE_SOURCES
+    with cf.ThreadPoolExecutor(max_workers=len(sources)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), sources))
+    _link(objs[:len(SOURCES)], LIB, verbose)
+    _link(objs[len(SOURCES):], PROBE_LIB, verbose)
     return LIB
 
 

@@ -114,3 +114,22 @@ def test_last_error_is_thread_local():
     t.join()
     assert seen["msg"] == ""
     assert "omega" in E._lib.elbm_last_error().decode()
+
+
+def test_probe_library_exports_its_header():
+    """The bandwidth probe (libelbm_probe.so) exports every function its header
+    declares, and sizes its buffers as the step's plane slabs (no GPU)."""
+    import ctypes as C
+    import os
+    import re
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    txt = re.sub(r"/\*.*?\*/", "", open(os.path.join(root, "include", "elbm_probe.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(elbm_probe_[a-z0-9_]+)\s*\(", txt)))
+    lib = C.CDLL(os.path.join(root, "paper_2101_04550_amd", "libelbm_probe.so"))
+    assert names and all(hasattr(lib, n) for n in names)
+    lib.elbm_probe_bytes.argtypes = [C.c_int32] * 4 + [C.POINTER(C.c_size_t)]
+    nb = C.c_size_t(0)
+    assert lib.elbm_probe_bytes(4, 256, 256, 256, C.byref(nb)) == 0
+    assert nb.value == 256 * 27 * 65536 * 4
+    assert lib.elbm_probe_bytes(3, 256, 256, 256, C.byref(nb)) == 1
