@@ -79,7 +79,9 @@ enum { ELBM_STORE_F32 = 0, ELBM_STORE_F16 = 1, ELBM_STORE_BF16 = 2 };
  *  extended     1: extended equilibrium (Sec. 2.3, eq. 27eqext);
  *               0: uncorrected product-form equilibrium (Sec. 2.3, eq. 27eq).
  *  diag_every   0: no automatic diagnostics; k > 0: elbm_step records the
- *               diagnostics of every k-th step into a device-resident history.
+ *               diagnostics of every k-th step into a device-resident history
+ *               (formed by that step's own kernel; needs 12 bytes per node
+ *               more device memory, see elbm_query_bytes).
  *  diag_capacity number of history records kept (ring buffer), >= 1 when
  *               diag_every > 0.
  *  mode_k[3]    physical wave vector k of the measured plane mode, and
@@ -169,8 +171,9 @@ int32_t elbm_validate(const elbm_params* params);
 /* Device bytes a lattice needs: two population buffers (ping-pong) of about
  * Q * N * sizeof(storage) bytes each (stored plane by plane along the slowest
  * axis, each direction's array of a plane padded to 64 elements) plus a small
- * fixed scratch area (descriptor, diagnostic partial sums, history). Pure
- * host arithmetic. */
+ * fixed scratch area (descriptor, diagnostic partial sums, history; with
+ * diag_every > 0 also 3 N floats of staged velocity and 16 bytes per node of
+ * each axis for the mode factors). Pure host arithmetic. */
 int32_t elbm_query_bytes(const elbm_params* params, size_t* bytes);
 
 /* Creates a lattice in the caller's device buffer `dev_buf` of `bytes`
@@ -193,8 +196,13 @@ int32_t elbm_init(elbm_handle h, const double* rho, const double* u);
  * per step one fused kernel that pulls, computes moments and the anomaly,
  * its central difference (Sec. 2.3, eq. Paastar1), the extended pressure,
  * the product form and relaxes (plus the force). Asynchronous on the
- * handle's stream. If diag_every > 0, diagnostics of every diag_every-th
- * step are appended to the history. */
+ * handle's stream. If diag_every > 0, every diag_every-th step runs the
+ * same kernel with the diagnostics folded in: it sums the FP64 moments of
+ * the pulled populations of each node, which are the moments of the node's
+ * post-collision state (the collision conserves rho and adds rho g to j), so
+ * the record equals elbm_diag of that state up to the rounding of the stored
+ * values; the record is appended to the history. The state after such a step
+ * is bitwise the state without diagnostics. */
 int32_t elbm_step(elbm_handle h, int64_t nsteps);
 
 /* Number of steps taken since elbm_init / elbm_set_populations. */
@@ -219,7 +227,8 @@ int32_t elbm_populations(elbm_handle h, double* f);
  * resets the step count and clears the history. Synchronises. */
 int32_t elbm_set_populations(elbm_handle h, const double* f);
 
-/* Computes the diagnostics of the current state now. Synchronises.
+/* Computes the diagnostics of the current (stored) state now, by a pass that
+ * reads it. Synchronises.
  * Returns ELBM_EUNSTABLE (with *out filled) if a node holds a non-finite
  * moment or rho <= 0. */
 int32_t elbm_diag(elbm_handle h, elbm_diag_record* out);

@@ -29,7 +29,9 @@ struct elbm_lattice {
   void* buf[2] = {nullptr, nullptr};
   TableHeader* hdr_dev = nullptr;
   LatticeDesc* desc_dev = nullptr;
-  double* partials = nullptr;
+  double* partials = nullptr;  // 2 kDiagBlocks records: moment sums, then enstrophy sums
+  float* ustage = nullptr;     // 3 N floats (diag_every > 0): velocity staged by the sample steps
+  double* mode_tab = nullptr;  // per-axis mode factors (diag_every > 0)
   double* history = nullptr;
   double* last = nullptr;
   int64_t* hist_count = nullptr;
@@ -40,6 +42,7 @@ struct elbm_lattice {
   bool wall = false, force = false, staged = false;
   LatticeDesc desc{};
   LatticeConst64 c64{};
+  DiagArgs dargs{};
 };
 
 struct elbm_batch_s {
@@ -127,7 +130,9 @@ struct Layout {
   int64_t N = 0, pstride = 0, plane = 0, nplanes = 0;
   size_t es = 4, pop_bytes = 0;
   size_t off_buf[2] = {0, 0};
-  size_t off_hdr = 0, off_desc = 0, off_partials = 0, off_hist = 0, off_last = 0, off_count = 0, total = 0;
+  size_t off_hdr = 0, off_desc = 0, off_partials = 0, off_ustage = 0, off_modetab = 0, off_hist = 0, off_last = 0,
+         off_count = 0, total = 0;
+  int64_t modetab_len = 0;  // (cos, sin) pairs: n_x + n_y (+ n_z)
   int32_t capacity = 0;
 };
 
@@ -218,7 +223,14 @@ Layout layout_of(const elbm_params* p) {
   L.off_desc = o;
   o = align_up(o + sizeof(LatticeDesc), kAlign);
   L.off_partials = o;
-  o = align_up(o + size_t(kDiagBlocks) * kRec * sizeof(double), kAlign);
+  o = align_up(o + 2 * size_t(kDiagBlocks) * kRec * sizeof(double), kAlign);
+  if (p->diag_every > 0) {
+    L.off_ustage = o;
+    o = align_up(o + 3 * size_t(L.N) * sizeof(float), kAlign);
+    for (int a = 0; a < L.D; ++a) L.modetab_len += p->n[a];
+    L.off_modetab = o;
+    o = align_up(o + 2 * size_t(L.modetab_len) * sizeof(double), kAlign);
+  }
   L.off_hist = o;
   o = align_up(o + size_t(L.capacity) * kRec * sizeof(double), kAlign);
   L.off_last = o;
@@ -337,6 +349,27 @@ void fill_desc(elbm_lattice* h) {
       c.W[a][k + 1] = on ? psi(k, c.uref[a], p.T + c.uref[a] * c.uref[a], c.lam[a]) : (k == 0 ? 1.0 : 0.0);
   }
   c.has_mode = (c.mode_dir[0] != 0.0 || c.mode_dir[1] != 0.0 || c.mode_dir[2] != 0.0) ? 1 : 0;
+}
+
+void fill_diag_args(elbm_lattice* h) {
+  const LatticeConst64& c = h->c64;
+  DiagArgs& d = h->dargs;
+  d.ustage = h->ustage;
+  d.partials = h->partials;
+  d.mode_tab = h->mode_tab;
+  int32_t off = 0;
+  for (int a = 0; a < 3; ++a) {
+    d.lam[a] = c.lam[a];
+    d.uref[a] = c.uref[a];
+    d.g[a] = c.g[a];
+    d.mode_dir[a] = c.mode_dir[a];
+    d.n[a] = c.n[a];
+    d.mode_off[a] = off;
+    if (a < h->D) off += c.n[a];
+  }
+  d.inv_scale = c.inv_scale;
+  d.N = c.N;
+  d.has_mode = c.has_mode;
 }
 
 int grid_for_tiles(int64_t ntiles) {
@@ -458,6 +491,10 @@ int32_t elbm_create(const elbm_params* p, void* dev_buf, size_t bytes, void* hip
   h->hdr_dev = reinterpret_cast<TableHeader*>(h->base + L.off_hdr);
   h->desc_dev = reinterpret_cast<LatticeDesc*>(h->base + L.off_desc);
   h->partials = reinterpret_cast<double*>(h->base + L.off_partials);
+  if (p->diag_every > 0) {
+    h->ustage = reinterpret_cast<float*>(h->base + L.off_ustage);
+    h->mode_tab = reinterpret_cast<double*>(h->base + L.off_modetab);
+  }
   h->history = reinterpret_cast<double*>(h->base + L.off_hist);
   h->last = reinterpret_cast<double*>(h->base + L.off_last);
   h->hist_count = reinterpret_cast<int64_t*>(h->base + L.off_count);
@@ -473,12 +510,31 @@ int32_t elbm_create(const elbm_params* p, void* dev_buf, size_t bytes, void* hip
     return hip_fail(e, "elbm_create");
   }
   fill_desc(h);
+  // per-axis factors e^{i k_a lam_a x} of the diagnostic mode (sample steps)
+  std::vector<double> mtab;
+  if (p->diag_every > 0) {
+    fill_diag_args(h);
+    if (h->c64.has_mode) {
+      mtab.resize(2 * size_t(L.modetab_len));
+      int64_t off = 0;
+      for (int a = 0; a < h->D; ++a) {
+        for (int64_t x = 0; x < p->n[a]; ++x) {
+          const double ph = h->c64.mode_k[a] * (double(x) * h->c64.lam[a]);
+          mtab[2 * (off + x)] = std::cos(ph);
+          mtab[2 * (off + x) + 1] = std::sin(ph);
+        }
+        off += p->n[a];
+      }
+    }
+  }
   TableHeader hdr{};
   hdr.count = 1;
   hdr.total_tiles = h->ntiles;
   e = hipMemcpyAsync(h->hdr_dev, &hdr, sizeof hdr, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(h->desc_dev, &h->desc, sizeof h->desc, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->hist_count, 0, sizeof(int64_t), h->stream);
+  if (e == hipSuccess && !mtab.empty())
+    e = hipMemcpyAsync(h->mode_tab, mtab.data(), mtab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
   // The padding of the direction arrays is never written by the kernels; it
   // starts (and stays) zero so that saved states are byte-identical whenever
   // the populations are.
@@ -523,14 +579,21 @@ int32_t elbm_step(elbm_handle h, int64_t nsteps) {
   int32_t s = set_dev(h->device);
   if (s) return s;
   const int grid = grid_for_tiles(h->ntiles);
+  const int grid_diag = std::min(grid, kDiagBlocks);
   for (int64_t k = 0; k < nsteps; ++k) {
-    HIPCHK(launch_step(h->D, h->p.storage, h->wall, h->force, h->staged, h->hdr_dev, h->desc_dev, h->step, grid,
-                       h->stream));
-    ++h->step;
-    if (h->p.diag_every > 0 && h->step % h->p.diag_every == 0) {
-      s = run_diag(h, true);
-      if (s) return s;
+    const bool sample = h->p.diag_every > 0 && (h->step + 1) % h->p.diag_every == 0;
+    if (sample) {
+      // the sample step: the step kernel also forms the record's moments
+      // (its tiles spread over at most kDiagBlocks blocks, one partial each)
+      HIPCHK(launch_step_diag(h->D, h->p.storage, h->wall, h->force, h->staged, h->hdr_dev, h->desc_dev, h->step,
+                              grid_diag, h->dargs, h->stream));
+      HIPCHK(launch_diag_tail(h->c64, h->ustage, h->partials, grid_diag, h->history, h->hist_count,
+                              int32_t(h->p.diag_capacity), h->last, h->step + 1, h->stream));
+    } else {
+      HIPCHK(launch_step(h->D, h->p.storage, h->wall, h->force, h->staged, h->hdr_dev, h->desc_dev, h->step, grid,
+                         h->stream));
     }
+    ++h->step;
   }
   return ELBM_OK;
 }

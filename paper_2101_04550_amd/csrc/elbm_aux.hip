@@ -289,20 +289,24 @@ __global__ void __launch_bounds__(kDiagThreads)
   if (threadIdx.x == 0) partials[blockIdx.x * kRec + R_ENS] = r;
 }
 
-// One block: fixed-order reduction of the per-block partials into a record.
-// The record goes to history[(*count) % capacity] and *count is incremented
-// when capacity > 0; it always goes to `last` (the record after the ring).
+// One block: fixed-order reduction of the per-block partials into a record:
+// the enstrophy from the nb_e records of `pens`, every other field from the
+// nb_m records of `pmom`. The record goes to history[(*count) % capacity]
+// and *count is incremented when capacity > 0; it always goes to `last` (the
+// record after the ring).
 __global__ void __launch_bounds__(kDiagThreads)
-    diag_final_kernel(const double* __restrict__ partials, int nblocks, double* __restrict__ history,
-                      int64_t* __restrict__ count, int32_t capacity, double* __restrict__ last, int64_t step,
-                      double ncells) {
+    diag_final_kernel(const double* __restrict__ pmom, int nb_m, const double* __restrict__ pens, int nb_e,
+                      double* __restrict__ history, int64_t* __restrict__ count, int32_t capacity,
+                      double* __restrict__ last, int64_t step, double ncells) {
   __shared__ double sh[kDiagThreads / 64];
   double rec[kRec];
   for (int f = 0; f < kRec; ++f) {
     const int kind = field_kind(f);
+    const double* part = f == R_ENS ? pens : pmom;
+    const int nblocks = f == R_ENS ? nb_e : nb_m;
     double x = kind == 0 ? 0.0 : (kind == 1 ? 0.0 : 1e300);
     for (int b = threadIdx.x; b < nblocks; b += kDiagThreads) {
-      const double v = partials[b * kRec + f];
+      const double v = part[b * kRec + f];
       x = kind == 0 ? x + v : (kind == 1 ? fmax(x, v) : fmin(x, v));
     }
     rec[f] = block_reduce(x, kind, sh);
@@ -405,11 +409,19 @@ hipError_t launch_diag(const LatticeConst64& c, const void* src, float* ustage, 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(diag_curl_kernel, dim3(nb), dim3(kDiagThreads), 0, st, c, ustage, partials);
-  e = hipGetLastError();
+  return launch_diag_tail(c, ustage, partials, nb, history, hist_count, capacity, last, step, st);
+}
+
+hipError_t launch_diag_tail(const LatticeConst64& c, const float* ustage, double* partials, int nb_moments,
+                            double* history, int64_t* hist_count, int32_t capacity, double* last, int64_t step,
+                            hipStream_t st) {
+  if (nb_moments < 1 || nb_moments > kDiagBlocks) return hipErrorInvalidValue;
+  double* pens = partials + size_t(kDiagBlocks) * kRec;
+  hipLaunchKernelGGL(diag_curl_kernel, dim3(kDiagBlocks), dim3(kDiagThreads), 0, st, c, ustage, pens);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kDiagThreads), 0, st, partials, nb, history, hist_count,
-                     capacity, last, step, double(c.N));
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kDiagThreads), 0, st, partials, nb_moments, pens,
+                     kDiagBlocks, history, hist_count, capacity, last, step, double(c.N));
   return hipGetLastError();
 }
 

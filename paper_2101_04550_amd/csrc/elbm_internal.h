@@ -108,6 +108,28 @@ struct LatticeConst64 {
   int32_t has_mode;
 };
 
+// Diagnostics folded into a step (sample steps of elbm_step): the step kernel
+// forms, per node, rho and the reported velocity u = j/rho + g/2 of its pulled
+// (post-streaming) populations in FP64. These are the moments of the step's
+// post-collision state at that node (the collision conserves rho and adds the
+// force impulse rho g to j, so j/rho + g/2 = j'/rho - g/2). The kernel
+// accumulates the FP64 sums of a diagnostic record per block (partials, fields
+// other than the enstrophy) and stages u in FP32 for the enstrophy pass.
+struct DiagArgs {
+  float* ustage;           // 3 N floats, component-major over the physical axes, node order x fastest
+  double* partials;        // kRec doubles per block of the launch
+  const double* mode_tab;  // (cos, sin) of mode_k[a] lam[a] x for x < n[a], axis a at mode_tab + 2 mode_off[a]
+  double lam[3];           // physical axes
+  double uref[3];
+  double g[3];
+  double mode_dir[3];
+  double inv_scale;
+  int64_t N;
+  int32_t n[3];            // physical extents
+  int32_t mode_off[3];
+  int32_t has_mode;
+};
+
 // ---- allocation-free batched runner (elbm_static.hip) ----
 constexpr int kStaticMaxLattices = 256;   // lattices per elbm_batch_run_static call
 constexpr int kStaticClasses = 48;        // kernel classes (one table each)
@@ -126,6 +148,12 @@ hipError_t launch_write_bytes(void* dst, const unsigned char* src, size_t bytes,
 // staged: the LDS-staged D3Q27 kernel for 16-bit storage (periodic, full tiles).
 hipError_t launch_step(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
                        const LatticeDesc* table, int64_t substep, int grid, hipStream_t st);
+// The same step with the diagnostics of its post-collision state folded in
+// (one lattice per table; grid at most kDiagBlocks blocks, one partial record
+// per block).
+hipError_t launch_step_diag(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
+                            const LatticeDesc* table, int64_t substep, int grid, const DiagArgs& da,
+                            hipStream_t st);
 int step_block_threads(int D, bool staged);
 // Resident step blocks per compute unit for a kernel class (occupancy query).
 int step_blocks_per_cu(int D, int storage, bool wall, bool force, bool staged);
@@ -137,9 +165,16 @@ hipError_t launch_pop_in(const LatticeConst64& c, const double* in, int i, void*
 hipError_t launch_field(const LatticeConst64& c, const void* src, int comp, double* out, hipStream_t st);
 // Diagnostics of the state in `src`: the record goes to `last`, and is also
 // appended to the ring `history` (capacity records, count in *hist_count)
-// when capacity > 0. `ustage` holds 3 N floats of scratch.
+// when capacity > 0. `ustage` holds 3 N floats of scratch; `partials` 2
+// kDiagBlocks records (the moment sums, then the enstrophy sums).
 hipError_t launch_diag(const LatticeConst64& c, const void* src, float* ustage, double* partials,
                        double* history, int64_t* hist_count, int32_t capacity, double* last,
                        int64_t step, hipStream_t st);
+// After a step with folded diagnostics (launch_step_diag, nb_moments partial
+// records in `partials`): the enstrophy pass over the staged velocity and the
+// final fixed-order reduction into `last` and the history.
+hipError_t launch_diag_tail(const LatticeConst64& c, const float* ustage, double* partials, int nb_moments,
+                            double* history, int64_t* hist_count, int32_t capacity, double* last, int64_t step,
+                            hipStream_t st);
 
 }  // namespace elbm

@@ -485,9 +485,163 @@ __device__ __forceinline__ void collide(const TileConst& k, float drho, const fl
   }
 }
 
-template <int D, int S, bool WALL, bool FORCE>
+// ---- diagnostics folded into a step ----
+// A node's record contribution is kDF FP64 values, in this order: mass, the
+// three momentum components, |u|^2, the mode's real and imaginary parts, the
+// mode's max |amplitude| (max), the least density (min) and the count of
+// non-finite nodes. Plane by plane, each 16-lane row of a wave folds its
+// nodes' values with DPP lane permutations, and lane (row r, field j) adds the
+// row's value of field j into LDS slot (wave, r, j); the block's partial
+// record is the fold of its slots in (wave, row) order. Every step of this is
+// fixed, so a record is reproducible bitwise for a given launch grid.
+constexpr int kDF = 10;
+constexpr int kDiagRows = 4;  // 16-lane rows per wave
+__device__ __forceinline__ constexpr int diag_kind(int j) { return j == 7 ? 1 : (j == 8 ? 2 : 0); }
+__device__ __forceinline__ constexpr double diag_identity(int j) { return j == 8 ? 1e300 : 0.0; }
+__device__ __forceinline__ double diag_op(int kind, double x, double y) {
+  return kind == 0 ? x + y : (kind == 1 ? fmax(x, y) : fmin(x, y));
+}
+// record field of accumulated value j
+__device__ __forceinline__ constexpr int diag_rec_field(int j) { return j + 1 + (j >= 5 ? 1 : 0); }
+
+// x of another lane of the same 16-lane row (DPP control CTRL), both halves
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const int l2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+
+// One node's contribution c[] from its pulled values hval(i) (storage scale):
+// rho and the reported velocity u = j/rho + g/2 in FP64; u is also staged in
+// FP32 for the enstrophy pass. (x0, x1, x2) are the node's internal indices
+// and cell its index with x fastest; internal axis a is physical axis a for
+// D3Q27, and 0 -> x, 2 -> y for D2Q9.
+// The node's value of field j goes to put(j, value) as soon as it is formed.
+template <int D, class HV, class PUT>
+__device__ __forceinline__ void diag_node(const DiagArgs& da, HV hval, int x0, int x1, int x2, int64_t cell,
+                                          PUT put) {
+  constexpr int Q = D == 3 ? 27 : 9;
+  double r = 0.0, m[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double v = double(hval(i));
+    r += v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int ci = cq<D>(i, a);
+      if (ci > 0) m[a] += v;
+      if (ci < 0) m[a] -= v;
+    }
+  }
+  const double mp[3] = {m[0], D == 3 ? m[1] : m[2], D == 3 ? m[2] : 0.0};
+  const double rho = 1.0 + r * da.inv_scale;
+  const double ir = 1.0 / rho;
+  double u[3];
+  bool finite = isfinite(rho);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = (a < D) ? (da.uref[a] + da.lam[a] * mp[a] * da.inv_scale) * ir + 0.5 * da.g[a] : 0.0;
+    finite = finite && isfinite(u[a]);
+    da.ustage[a * da.N + cell] = float(u[a]);
+  }
+  put(0, rho);
+  put(1, rho * u[0]);
+  put(2, rho * u[1]);
+  put(3, rho * u[2]);
+  put(4, u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  put(8, finite ? rho : -1e300);
+  put(9, finite ? 0.0 : 1.0);
+  double mre = 0.0, mim = 0.0, mabs = 0.0;
+  if (da.has_mode) {
+    // e^{i k.x} as the product of the per-axis factors e^{i k_a lam_a x_a}
+    const int xp[3] = {x0, D == 3 ? x1 : x2, D == 3 ? x2 : 0};
+    const double* e = da.mode_tab + 2 * (da.mode_off[0] + xp[0]);
+    double cs = e[0], sn = e[1];
+#pragma unroll
+    for (int a = 1; a < D; ++a) {
+      e = da.mode_tab + 2 * (da.mode_off[a] + xp[a]);
+      const double ca = e[0], sa = e[1];
+      const double c2 = cs * ca - sn * sa;
+      sn = sn * ca + cs * sa;
+      cs = c2;
+    }
+    const double up = da.mode_dir[0] * u[0] + da.mode_dir[1] * u[1] + da.mode_dir[2] * u[2];
+    mre = up * cs;
+    mim = -up * sn;
+    mabs = fabs(up);
+  }
+  put(5, mre);
+  put(6, mim);
+  put(7, mabs);
+}
+
+__device__ __forceinline__ void diag_clear(double (&c)[kDF]) {
+#pragma unroll
+  for (int j = 0; j < kDF; ++j) c[j] = diag_identity(j);
+}
+
+// Row fold of one field's value (see diag_wave_fold), and its store by the
+// lanes jl == j: for a caller with the whole wave active.
+__device__ __forceinline__ void diag_fold_one(int j, double x, double* __restrict__ wslot) {
+  const int kind = diag_kind(j);
+  x = diag_op(kind, x, dpp64<0xB1>(x));
+  x = diag_op(kind, x, dpp64<0x4E>(x));
+  x = diag_op(kind, x, dpp64<0x141>(x));
+  x = diag_op(kind, x, dpp64<0x140>(x));
+  const int lane = threadIdx.x & 63;
+  if ((lane & 15) == j) wslot[(lane >> 4) * kDF + j] = diag_op(kind, wslot[(lane >> 4) * kDF + j], x);
+}
+
+// Row fold of c[] (lanes i and i^1, i^2, then the mirrored lanes of each
+// half row and of the row: each pairwise operation is commutative, so all
+// 16 lanes of a row end with the same values), then lane (r, j) adds the
+// row's field j into wslot[r kDF + j]. Called by every lane of the wave.
+__device__ __forceinline__ void diag_wave_fold(double (&c)[kDF], double* __restrict__ wslot) {
+#pragma unroll
+  for (int j = 0; j < kDF; ++j) {
+    const int kind = diag_kind(j);
+    double x = c[j];
+    x = diag_op(kind, x, dpp64<0xB1>(x));   // quad_perm [1,0,3,2]
+    x = diag_op(kind, x, dpp64<0x4E>(x));   // quad_perm [2,3,0,1]
+    x = diag_op(kind, x, dpp64<0x141>(x));  // row_half_mirror
+    x = diag_op(kind, x, dpp64<0x140>(x));  // row_mirror
+    c[j] = x;
+  }
+  const int lane = threadIdx.x & 63, jl = lane & 15, r = lane >> 4;
+  double v = c[0];
+  int kind = 0;
+#pragma unroll
+  for (int j = 1; j < kDF; ++j) {
+    v = jl == j ? c[j] : v;
+    kind = jl == j ? diag_kind(j) : kind;
+  }
+  if (jl < kDF) wslot[r * kDF + jl] = diag_op(kind, wslot[r * kDF + jl], v);
+}
+
+__device__ __forceinline__ void diag_slots_init(double* __restrict__ wslot) {
+  const int lane = threadIdx.x & 63, jl = lane & 15, r = lane >> 4;
+  if (jl < kDF) wslot[r * kDF + jl] = jl == 8 ? 1e300 : 0.0;
+}
+
+// The block's partial record from its slots, folded in (wave, row) order.
+template <int NW>
+__device__ __forceinline__ void diag_block_store(const double* __restrict__ wsum, double* __restrict__ partials) {
+  __syncthreads();
+  const int j = threadIdx.x;
+  if (j < kDF) {
+    const int kind = j == 7 ? 1 : (j == 8 ? 2 : 0);
+    double r = wsum[j];
+    for (int k = 1; k < NW * kDiagRows; ++k) r = diag_op(kind, r, wsum[k * kDF + j]);
+    partials[blockIdx.x * kRec + (j + 1 + (j >= 5 ? 1 : 0))] = r;
+  }
+  if (j == kDF) partials[blockIdx.x * kRec + R_STEP] = 0.0;
+}
+
+template <int D, int S, bool WALL, bool FORCE, bool DIAG>
 __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, int64_t tl, int parity,
-                                          float* __restrict__ sq) {
+                                          float* __restrict__ sq, const DiagArgs& da, double* __restrict__ wslot) {
   using G = Geo<D, S>;
   using T = typename Store<S>::T;
   using P = Puller<D, S, WALL>;
@@ -727,6 +881,8 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
     }
     const float qnext = ghost_next ? -qc[2] : qn[2];
 
+    double dc[DIAG ? kDF : 1];
+    if constexpr (DIAG) diag_clear(dc);
     if (active) {
       // ---- collision of plane z ----
       drain_all();
@@ -745,7 +901,12 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
       collide<D, FORCE, S == 0>(k, drho, dj, Gd, [&](int i) { return h.get(i); },
                         [&](int i, float o) { Store<S>::store(rd, no.own, i * sb, o); });
+      if constexpr (DIAG)
+        diag_node<D>(da, [&](int i) { return h.get(i); }, gx, gy, z,
+                     int64_t(gx) + int64_t(k.n0) * (int64_t(gy) + int64_t(k.n1) * z),
+                     [&](int j, double v) { dc[j] = v; });
     }
+    if constexpr (DIAG) diag_wave_fold(dc, wslot);
     drain_vm();
 
     if (more && active) {
@@ -838,9 +999,10 @@ struct Held {
 // a wall takes the populations that would arrive through it from its own
 // post-collision populations of the opposite directions, loaded directly, and
 // the anomaly beyond the wall is the odd ghost -Q~ of the wall row.
-template <int S, bool FORCE, bool WALLY>
+template <int S, bool FORCE, bool WALLY, bool DIAG>
 __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld, int64_t tl, int parity,
-                                              unsigned char* __restrict__ smem) {
+                                              unsigned char* __restrict__ smem, const DiagArgs& da,
+                                              double* __restrict__ wslot) {
   using namespace lds;
   using T = typename Store<S>::T;
   using R = typename Store<S>::R;
@@ -1077,6 +1239,15 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
     // updated (on the last plane there is none that the tile reads)
     if (m + 2 <= len) stage_load(plane_index(z + 2 * dir), fre);
 
+    if constexpr (DIAG) {
+      // the record's moments of plane z, from its held pulled values (here,
+      // before the next plane's values are held too)
+      // (every lane holds a node: each field is folded as soon as it is formed)
+      diag_node<3>(da, [&](int i) { return Store<S>::to_float(cur.get(i)); }, gx, gy, z,
+                   int64_t(gx) + int64_t(k.n0) * (int64_t(gy) + int64_t(k.n1) * z),
+                   [&](int j, double v) { diag_fold_one(j, v, wslot); });
+    }
+
     // next plane: values (kept for its relaxation), own anomaly (closes the
     // ring) and the halo's
     float drn, djn[3], qn[3];
@@ -1122,9 +1293,10 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
   }
 }
 
-template <int S, bool FORCE, bool WALLY>
+template <int S, bool FORCE, bool WALLY, bool DIAG>
 __global__ void __launch_bounds__(lds::NT)
-    step_kernel_lds(const TableHeader* __restrict__ hdr, const LatticeDesc* __restrict__ table, int64_t substep) {
+    step_kernel_lds(const TableHeader* __restrict__ hdr, const LatticeDesc* __restrict__ table, int64_t substep,
+                    DiagArgs da) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[lds::BYTES];
   const int64_t total = hdr->total_tiles;
   const int count = hdr->count;
@@ -1134,22 +1306,28 @@ __global__ void __launch_bounds__(lds::NT)
   const int64_t per = (total + 7) >> 3;
   const int64_t tb = xcd * per;
   const int64_t te = min(tb + per, total);
+  __shared__ double wsum[DIAG ? (lds::NT / 64) * kDiagRows * kDF : 1];
+  double* const wslot = wsum + (DIAG ? (threadIdx.x >> 6) * kDiagRows * kDF : 0);
+  if constexpr (DIAG) diag_slots_init(wslot);
   int L = 0;
   for (int64_t t = tb + lb; t < te; t += gpx) {
     while (L + 1 < count && table[L + 1].tile_base <= t) ++L;
     const LatticeDesc* d = table + L;
     if (substep < d->nsteps) {
       const int parity = (d->parity0 + int(substep & 1)) & 1;
-      step_tile_lds<S, FORCE, WALLY>(d, t - d->tile_base, parity, smem);
+      step_tile_lds<S, FORCE, WALLY, DIAG>(d, t - d->tile_base, parity, smem, da, wslot);
     }
     __syncthreads();
   }
+  if constexpr (DIAG) diag_block_store<lds::NT / 64>(wsum, da.partials);
 }
 
-template <int D, int S, bool WALL, bool FORCE>
+template <int D, int S, bool WALL, bool FORCE, bool DIAG>
 __global__ void __launch_bounds__(Threads<D>::value)
-    step_kernel(const TableHeader* __restrict__ hdr, const LatticeDesc* __restrict__ table, int64_t substep) {
-  __shared__ float sq[Geo<D, S>::LDS];
+    step_kernel(const TableHeader* __restrict__ hdr, const LatticeDesc* __restrict__ table, int64_t substep,
+                DiagArgs da) {
+  __shared__ __attribute__((aligned(16))) float sq[Geo<D, S>::LDS];
+  __shared__ double wsum[DIAG ? (Threads<D>::value / 64) * kDiagRows * kDF : 1];
   const int64_t total = hdr->total_tiles;
   const int count = hdr->count;
   const int gpx = gridDim.x >> 3;  // blocks per XCD (grid is a multiple of 8)
@@ -1158,50 +1336,63 @@ __global__ void __launch_bounds__(Threads<D>::value)
   const int64_t per = (total + 7) >> 3;
   const int64_t tb = xcd * per;
   const int64_t te = min(tb + per, total);
+  double* const wslot = wsum + (DIAG ? (threadIdx.x >> 6) * kDiagRows * kDF : 0);
+  if constexpr (DIAG) diag_slots_init(wslot);
   int L = 0;
   for (int64_t t = tb + lb; t < te; t += gpx) {
     while (L + 1 < count && table[L + 1].tile_base <= t) ++L;
     const LatticeDesc* d = table + L;
     if (substep < d->nsteps) {
       const int parity = (d->parity0 + int(substep & 1)) & 1;
-      step_tile<D, S, WALL, FORCE>(d, t - d->tile_base, parity, sq);
+      step_tile<D, S, WALL, FORCE, DIAG>(d, t - d->tile_base, parity, sq, da, wslot);
     }
     __syncthreads();
   }
+  if constexpr (DIAG) diag_block_store<Threads<D>::value / 64>(wsum, da.partials);
 }
 
 template <int D, int S, bool WALL, bool FORCE>
 hipError_t launch_one(const TableHeader* hdr, const LatticeDesc* table, int64_t substep, int grid,
-                      hipStream_t st) {
-  hipLaunchKernelGGL((step_kernel<D, S, WALL, FORCE>), dim3(grid), dim3(Geo<D, S>::NT), 0, st, hdr, table,
-                     substep);
+                      const DiagArgs* da, hipStream_t st) {
+  if (da)
+    hipLaunchKernelGGL((step_kernel<D, S, WALL, FORCE, true>), dim3(grid), dim3(Geo<D, S>::NT), 0, st, hdr, table,
+                       substep, *da);
+  else
+    hipLaunchKernelGGL((step_kernel<D, S, WALL, FORCE, false>), dim3(grid), dim3(Geo<D, S>::NT), 0, st, hdr,
+                       table, substep, DiagArgs{});
   return hipGetLastError();
 }
 
 template <int D, int S>
 hipError_t launch_ds(bool wall, bool force, const TableHeader* hdr, const LatticeDesc* table, int64_t s,
-                     int grid, hipStream_t st) {
+                     int grid, const DiagArgs* da, hipStream_t st) {
   if (wall) {
-    return force ? launch_one<D, S, true, true>(hdr, table, s, grid, st)
-                 : launch_one<D, S, true, false>(hdr, table, s, grid, st);
+    return force ? launch_one<D, S, true, true>(hdr, table, s, grid, da, st)
+                 : launch_one<D, S, true, false>(hdr, table, s, grid, da, st);
   }
-  return force ? launch_one<D, S, false, true>(hdr, table, s, grid, st)
-               : launch_one<D, S, false, false>(hdr, table, s, grid, st);
+  return force ? launch_one<D, S, false, true>(hdr, table, s, grid, da, st)
+               : launch_one<D, S, false, false>(hdr, table, s, grid, da, st);
 }
 
 template <int S, bool FORCE, bool WALLY>
-hipError_t launch_lds(const TableHeader* hdr, const LatticeDesc* table, int64_t substep, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((step_kernel_lds<S, FORCE, WALLY>), dim3(grid), dim3(lds::NT), 0, st, hdr, table, substep);
+hipError_t launch_lds(const TableHeader* hdr, const LatticeDesc* table, int64_t substep, int grid,
+                      const DiagArgs* da, hipStream_t st) {
+  if (da)
+    hipLaunchKernelGGL((step_kernel_lds<S, FORCE, WALLY, true>), dim3(grid), dim3(lds::NT), 0, st, hdr, table,
+                       substep, *da);
+  else
+    hipLaunchKernelGGL((step_kernel_lds<S, FORCE, WALLY, false>), dim3(grid), dim3(lds::NT), 0, st, hdr, table,
+                       substep, DiagArgs{});
   return hipGetLastError();
 }
 
 template <int S>
 hipError_t launch_lds_s(bool wall, bool force, const TableHeader* hdr, const LatticeDesc* table, int64_t s,
-                        int grid, hipStream_t st) {
-  if (wall) return force ? launch_lds<S, true, true>(hdr, table, s, grid, st)
-                         : launch_lds<S, false, true>(hdr, table, s, grid, st);
-  return force ? launch_lds<S, true, false>(hdr, table, s, grid, st)
-               : launch_lds<S, false, false>(hdr, table, s, grid, st);
+                        int grid, const DiagArgs* da, hipStream_t st) {
+  if (wall) return force ? launch_lds<S, true, true>(hdr, table, s, grid, da, st)
+                         : launch_lds<S, false, true>(hdr, table, s, grid, da, st);
+  return force ? launch_lds<S, true, false>(hdr, table, s, grid, da, st)
+               : launch_lds<S, false, false>(hdr, table, s, grid, da, st);
 }
 
 }  // namespace
@@ -1211,7 +1402,7 @@ int step_block_threads(int D, bool staged) { return staged ? lds::NT : (D == 3 ?
 template <int D, int S, bool WALL, bool FORCE>
 int occupancy_one() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<D, S, WALL, FORCE>, Geo<D, S>::NT, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<D, S, WALL, FORCE, false>, Geo<D, S>::NT, 0) !=
       hipSuccess)
     return 1;
   return n > 0 ? n : 1;
@@ -1220,7 +1411,8 @@ int occupancy_one() {
 template <int S, bool FORCE, bool WALLY>
 int occupancy_lds() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_lds<S, FORCE, WALLY>, lds::NT, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_lds<S, FORCE, WALLY, false>, lds::NT, 0) !=
+      hipSuccess)
     return 1;
   return n > 0 ? n : 1;
 }
@@ -1254,29 +1446,43 @@ int step_blocks_per_cu(int D, int storage, bool wall, bool force, bool staged) {
   }
 }
 
-hipError_t launch_step(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
-                       const LatticeDesc* table, int64_t substep, int grid, hipStream_t st) {
+namespace {
+hipError_t launch_any(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
+                      const LatticeDesc* table, int64_t substep, int grid, const DiagArgs* da, hipStream_t st) {
   if (grid <= 0 || (grid & 7)) return hipErrorInvalidConfiguration;
   if (staged) {
     // (wall: bounce-back on y only; the host admits no other walls here)
     if (D != 3 || (storage != 1 && storage != 2)) return hipErrorInvalidValue;
-    return storage == 1 ? launch_lds_s<1>(wall, force, hdr, table, substep, grid, st)
-                        : launch_lds_s<2>(wall, force, hdr, table, substep, grid, st);
+    return storage == 1 ? launch_lds_s<1>(wall, force, hdr, table, substep, grid, da, st)
+                        : launch_lds_s<2>(wall, force, hdr, table, substep, grid, da, st);
   }
   if (D == 3) {
     switch (storage) {
-      case 0: return launch_ds<3, 0>(wall, force, hdr, table, substep, grid, st);
-      case 1: return launch_ds<3, 1>(wall, force, hdr, table, substep, grid, st);
-      case 2: return launch_ds<3, 2>(wall, force, hdr, table, substep, grid, st);
+      case 0: return launch_ds<3, 0>(wall, force, hdr, table, substep, grid, da, st);
+      case 1: return launch_ds<3, 1>(wall, force, hdr, table, substep, grid, da, st);
+      case 2: return launch_ds<3, 2>(wall, force, hdr, table, substep, grid, da, st);
     }
   } else if (D == 2) {
     switch (storage) {
-      case 0: return launch_ds<2, 0>(wall, force, hdr, table, substep, grid, st);
-      case 1: return launch_ds<2, 1>(wall, force, hdr, table, substep, grid, st);
-      case 2: return launch_ds<2, 2>(wall, force, hdr, table, substep, grid, st);
+      case 0: return launch_ds<2, 0>(wall, force, hdr, table, substep, grid, da, st);
+      case 1: return launch_ds<2, 1>(wall, force, hdr, table, substep, grid, da, st);
+      case 2: return launch_ds<2, 2>(wall, force, hdr, table, substep, grid, da, st);
     }
   }
   return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_step(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
+                       const LatticeDesc* table, int64_t substep, int grid, hipStream_t st) {
+  return launch_any(D, storage, wall, force, staged, hdr, table, substep, grid, nullptr, st);
+}
+
+hipError_t launch_step_diag(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
+                            const LatticeDesc* table, int64_t substep, int grid, const DiagArgs& da,
+                            hipStream_t st) {
+  if (grid > kDiagBlocks || !da.ustage || !da.partials) return hipErrorInvalidValue;
+  return launch_any(D, storage, wall, force, staged, hdr, table, substep, grid, &da, st);
 }
 
 }  // namespace elbm

@@ -93,11 +93,15 @@ def test_footprint_covers_two_population_buffers(n, storage, es):
     N = math.prod(n)
     pops = 2 * Q * N * es
     assert b >= pops
-    # fixed scratch (descriptor, partial sums, one record) stays small
-    assert b - pops < 2 * Q * 256 * es + 2 * 4096 + 256 * 1024
-    # history adds capacity * 16 doubles
+    # padding and fixed scratch (descriptor, two sets of 1024 partial records
+    # of 16 doubles, one record) stay small
+    assert b - pops < 2 * Q * 256 * es + 2 * 4096 + 256 * 1024 + 1024 * 16 * 8
+    # sampled diagnostics add the history (capacity * 16 doubles), the staged
+    # velocity of a sample step (3 N floats) and the mode factors (2 doubles
+    # per node of each axis)
     p2 = E.make_params(n, T=1 / 3, omega=1.5, storage=storage, diag_every=10, diag_capacity=1000)
-    assert E.query_bytes(p2) - b >= 1000 * 16 * 8
+    extra = 1000 * 16 * 8 + 3 * N * 4 + 2 * sum(n) * 8
+    assert extra <= E.query_bytes(p2) - b < extra + 4 * 256
 
 
 def test_last_error_is_thread_local():
