@@ -1,0 +1,144 @@
+"""Pins of the open-boundary oracle (oracle/elbm_faces.py): properties its
+rules must have whatever the reading, checked without the GPU."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import elbm_faces as OF
+
+
+@pytest.mark.parametrize("lam", [(1.0, 1.0), (2.0, 1.0), (1.0, 1.4)])
+def test_grad_populations_carry_the_moments_they_are_built_from(lam):
+    g = np.random.default_rng(11)
+    c = O.velocity_set(2)
+    T = 1 / 3 if lam == (1.0, 1.0) else 0.5
+    for _ in range(5):
+        rho = 1.0 + 0.1 * g.standard_normal()
+        u = 0.05 * g.standard_normal(2)
+        A = 1e-3 * g.standard_normal((2, 2))
+        Pi = A + A.T
+        f = OF.grad_populations(rho, u, Pi, T, lam, c)
+        v = c * np.array(lam)[None, :]
+        assert f.sum() == pytest.approx(rho, abs=1e-14)
+        for a in range(2):
+            assert (v[:, a] * f).sum() == pytest.approx(rho * u[a], abs=1e-14)
+        for a, b in itertools.product(range(2), range(2)):
+            want = rho * ((T if a == b else 0.0) + u[a] * u[b]) + Pi[a, b]
+            assert (v[:, a] * v[:, b] * f).sum() == pytest.approx(want, abs=1e-14), (a, b)
+
+
+def _uniform(n, lam, T, u0):
+    nx, ny = n
+    rho = np.ones((ny, nx))
+    u = np.zeros((2, ny, nx))
+    u[0] = u0[0]
+    u[1] = u0[1]
+    return O.equilibrium(rho, u, T, lam, O.velocity_set(2))
+
+
+@pytest.mark.parametrize("lam", [(1.0, 1.0), (2.0, 1.0)])
+def test_uniform_stream_through_inlet_and_outlet_stays_uniform(lam):
+    """Inlet (x-), outlet (x+), symmetry planes (y-, y+): the uniform stream
+    at the inlet velocity is a steady state of every rule, including the
+    anomaly ghosts (on lambda_x = 2 the anomaly Q~_x is nonzero but uniform,
+    so its ghost must be even at inlet and outlet)."""
+    n = (12, 7)
+    T = 1 / 3
+    u0 = (0.05, 0.0)
+    p = O.Params(n=n, lam=lam, T=T, omega=1.7)
+    fc = OF.Faces(n, [OF.INLET, OF.OUTLET, OF.SYMMETRY, OF.SYMMETRY], inlet_velocity=(u0, u0, u0, u0))
+    f0 = _uniform(n, lam, T, u0)
+    f = OF.run_open(f0, p, fc, 40)
+    assert np.abs(f - f0).max() < 1e-14
+
+
+def _mirror_y(f, c):
+    """Populations of the mirror image about the plane between rows."""
+    Q = c.shape[0]
+    out = np.empty_like(f)
+    for i in range(Q):
+        cm = c[i].copy()
+        cm[1] = -cm[1]
+        k = int(np.where((c == cm).all(axis=1))[0][0])
+        out[k] = f[i][::-1, :]
+    return out
+
+
+@pytest.mark.parametrize("lam", [(1.0, 1.0), (2.0, 1.0)])
+def test_symmetry_plane_reproduces_the_mirrored_walled_channel(lam):
+    """A channel between Grad walls (y- and y+) whose state is mirror
+    symmetric about its centre plane equals, in its lower half, the half
+    channel with a wall at y- and a symmetry plane at y+: checks the specular
+    rule, the odd anomaly ghost and that the wall rule of a high face is the
+    mirror of the low face's."""
+    c = O.velocity_set(2)
+    nx, m = 6, 5
+    T = 0.5 if lam[0] == 2.0 else 1 / 3
+    g = np.random.default_rng(3)
+    p_full = O.Params(n=(nx, 2 * m), lam=lam, T=T, omega=1.6, force=(2e-5, 0.0))
+    p_half = O.Params(n=(nx, m), lam=lam, T=T, omega=1.6, force=(2e-5, 0.0))
+    rho = 1.0 + 0.01 * g.standard_normal((m, nx))
+    u = 0.02 * g.standard_normal((2, m, nx))
+    fh = O.equilibrium(rho, u, T, lam, c) * (1.0 + 0.002 * g.standard_normal((9, m, nx)))
+    ff = np.concatenate([fh, _mirror_y(fh, c)], axis=1)
+    full = OF.Faces((nx, 2 * m), [OF.PERIODIC, OF.PERIODIC, OF.WALL, OF.WALL])
+    half = OF.Faces((nx, m), [OF.PERIODIC, OF.PERIODIC, OF.WALL, OF.SYMMETRY])
+    for _ in range(15):
+        ff = OF.step_open(ff, p_full, full)
+        fh = OF.step_open(fh, p_half, half)
+    assert np.abs(ff[:, :m, :] - fh).max() < 1e-14
+    assert np.abs(ff - _mirror_y(ff, c)).max() < 1e-14
+
+
+def _poiseuille_error(ny, lam_x=1.0):
+    T, omega, g = 1 / 3, 1.0, 1e-6
+    nx = 3
+    lam = (lam_x, 1.0)
+    p = O.Params(n=(nx, ny), lam=lam, T=T, omega=omega, force=(g, 0.0))
+    fc = OF.Faces((nx, ny), [OF.PERIODIC, OF.PERIODIC, OF.WALL, OF.WALL])
+    f = _uniform((nx, ny), lam, T, (0.0, 0.0))
+    prev = None
+    for it in range(400):
+        f = OF.run_open(f, p, fc, 50)
+        _, u = O.velocity(f, p)
+        prof = u[0][:, 0]
+        if prev is not None and np.abs(prof - prev).max() < 1e-12 * np.abs(prof).max():
+            break
+        prev = prof
+    y = (np.arange(ny) + 0.5)  # distance from the wall at -1/2
+    H = float(ny)
+    exact = g / (2.0 * p.nu) * y * (H - y)
+    return float(np.sqrt(np.mean((prof - exact) ** 2)) / np.sqrt(np.mean(exact ** 2)))
+
+
+def test_grad_walls_converge_to_the_poiseuille_parabola_at_second_order():
+    """Force-driven channel between Grad walls (periodic x): the steady
+    velocity profile approaches the Navier-Stokes parabola through the
+    halfway walls, and halving the node spacing cuts the error by about 4."""
+    # (measured: 9.5e-2 at 6 rows, 2.38e-2 at 12, 5.9e-3 at 24: the straight
+    # line from the wall through the inward neighbour misses the parabola's
+    # curvature over one and a half node spacings)
+    e6 = _poiseuille_error(6)
+    e12 = _poiseuille_error(12)
+    assert e12 < 3e-2
+    assert 3.6 < e6 / e12 < 4.4, (e6, e12)
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.6])
+@pytest.mark.parametrize("lam,T", [((1.0, 1.0), 1 / 3), ((2.0, 1.0), 0.5)])
+def test_grad_walls_hold_couette_flow_linear(omega, lam, T):
+    """Plane Couette flow between a resting Grad wall (y-) and one moving at
+    u_w (y+): the steady profile is the straight line from 0 to u_w through
+    the two halfway walls, to 1e-8 of u_w. The wall's non-equilibrium
+    stress decides it: with its sign reversed the profile misses by 24%, and
+    without it by 8%."""
+    ny, nx, uw = 8, 3, 0.01
+    p = O.Params(n=(nx, ny), lam=lam, T=T, omega=omega)
+    fc = OF.Faces((nx, ny), [OF.PERIODIC, OF.PERIODIC, OF.WALL, OF.WALL], wall_velocity=(0.0, 0.0, 0.0, uw))
+    f = OF.run_open(_uniform((nx, ny), lam, T, (0.0, 0.0)), p, fc, 3000)
+    _, u = O.velocity(f, p)
+    y = np.arange(ny) + 0.5
+    assert np.abs(u[0][:, 0] - uw * y / ny).max() < 1e-8 * uw
+    assert np.abs(u[1]).max() < 1e-14
