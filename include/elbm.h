@@ -299,6 +299,75 @@ int32_t elbm_batch_destroy(elbm_batch b);
 #define ELBM_STATIC_MAX_LATTICES 256
 int32_t elbm_batch_run_static(const elbm_handle* hs, const int64_t* steps, int32_t count, void* hip_stream);
 
+/* ---- Open boundaries of a D2Q9 lattice ----
+ * The paper's wall-bounded cases use Grad's approximation for the walls
+ * (Sec. 3, opening paragraph, after a cited reference that it does not
+ * restate); its flat plate (Sec. 3.4) also needs an inlet, an outlet and a
+ * symmetry plane. The faces below implement one reading of these (stated in
+ * full in csrc/elbm_faces.hip); each face of the fluid rectangle has a kind
+ * per face node:
+ *  ELBM_FACE_PERIODIC  the axis is periodic (both faces, every node)
+ *  ELBM_FACE_SYMMETRY  free-slip plane halfway outside the boundary row
+ *                      (specular reflection)
+ *  ELBM_FACE_WALL      no-slip wall halfway outside the boundary row, moving
+ *                      tangentially at wall_velocity[f]; the populations
+ *                      entering from the wall are Grad's approximation at a
+ *                      velocity interpolated through the wall, the density
+ *                      of the node's mass and normal-momentum balance and
+ *                      the Navier-Stokes stress of the interpolated velocity
+ *  ELBM_FACE_INLET     prescribed velocity inlet_velocity[f] (equilibrium at
+ *                      the inward neighbour's density)
+ *  ELBM_FACE_OUTLET    zero gradient (the inward neighbour's populations)
+ * Faces are indexed 0: x-, 1: x+, 2: y-, 3: y+. A corner node (on two
+ * non-periodic faces) follows its x face, which must then be INLET or
+ * OUTLET. */
+enum {
+  ELBM_FACE_PERIODIC = 0,
+  ELBM_FACE_SYMMETRY = 1,
+  ELBM_FACE_WALL = 2,
+  ELBM_FACE_INLET = 3,
+  ELBM_FACE_OUTLET = 4
+};
+
+/*  abi_version     ELBM_ABI_VERSION
+ *  kind[4]         kind of every node of face f, unless node_kind[f] is set
+ *  node_kind[4]    NULL or a host array of one kind per fluid node along
+ *                  face f (n_y for x faces, n_x for y faces; read at create)
+ *  wall_velocity   tangential velocity of the WALL nodes of face f
+ *  inlet_velocity  (u_x, u_y) of the INLET nodes of face f */
+typedef struct elbm_faces_params {
+  uint32_t abi_version;
+  int32_t kind[4];
+  const int8_t* node_kind[4];
+  double wall_velocity[4];
+  double inlet_velocity[4][2];
+} elbm_faces_params;
+
+typedef struct elbm_faces_s* elbm_faces_handle;
+
+/* Device bytes of the face tables of `lattice` (node lists, ghost list,
+ * per-node moments). The lattice must be D2Q9 with FP32 storage, u_adv = 0
+ * and both axes periodic (bc), and it must carry the ghost ring: its
+ * extents are the fluid extents plus 2 along every axis whose faces are not
+ * PERIODIC (fluid extents >= 3 there). ELBM_EINVAL / ELBM_EUNSUPPORTED with
+ * a message otherwise. Host arithmetic only. */
+int32_t elbm_faces_query_bytes(elbm_handle lattice, const elbm_faces_params* fp, size_t* bytes);
+
+/* Attaches the faces to `lattice`, with their tables in the caller's device
+ * buffer (>= elbm_faces_query_bytes, 256-byte aligned); uploads on the
+ * lattice's stream and synchronises. The lattice must outlive the handle. */
+int32_t elbm_faces_create(elbm_handle lattice, const elbm_faces_params* fp, void* dev_buf, size_t bytes,
+                          elbm_faces_handle* out);
+
+/* Advances the lattice by nsteps steps, each preceded by the face update of
+ * the ghost ring (three small kernels on the lattice's stream), as
+ * elbm_step does otherwise (diagnostic samples included; they and
+ * elbm_fields cover the ghost ring too). Asynchronous. */
+int32_t elbm_faces_step(elbm_faces_handle f, int64_t nsteps);
+
+/* Releases the host handle (the device buffer stays the caller's). */
+int32_t elbm_faces_destroy(elbm_faces_handle f);
+
 #ifdef __cplusplus
 }
 #endif

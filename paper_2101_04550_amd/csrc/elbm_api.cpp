@@ -1014,3 +1014,203 @@ int32_t elbm_batch_run_static(const elbm_handle* hs, const int64_t* steps, int32
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- open faces
+
+struct elbm_faces_s {
+  elbm_lattice* h = nullptr;
+  FaceArgs args{};
+};
+
+namespace {
+
+struct FacePlan {
+  std::vector<FaceNode> nodes;  // boundary nodes on one face, then corner nodes
+  int32_t n_single = 0, n_corner = 0;
+  std::vector<FaceGhost> ghosts;
+  int32_t o[2] = {0, 0}, n[2] = {0, 0};
+  size_t off_nodes = 0, off_ghosts = 0, off_mom = 0, bytes = 0;
+};
+
+bool face_odd(int kind) { return kind == ELBM_FACE_SYMMETRY || kind == ELBM_FACE_WALL; }
+
+int32_t plan_faces(const elbm_lattice* h, const elbm_faces_params* fp, FacePlan& P) {
+  if (!h || !fp) return fail(ELBM_EINVAL, "NULL argument");
+  if (fp->abi_version != ELBM_ABI_VERSION) return fail(ELBM_EINVAL, "faces abi_version mismatch");
+  if (h->D != 2) return fail(ELBM_EUNSUPPORTED, "open faces are implemented for D2Q9 lattices only");
+  if (h->p.storage != ELBM_STORE_F32) return fail(ELBM_EUNSUPPORTED, "open faces need FP32 storage");
+  if (h->p.u_adv[0] != 0.0 || h->p.u_adv[1] != 0.0)
+    return fail(ELBM_EUNSUPPORTED, "open faces need u_adv == 0 (rest reference)");
+  if (h->p.bc[0] != ELBM_BC_PERIODIC || h->p.bc[1] != ELBM_BC_PERIODIC)
+    return fail(ELBM_EINVAL, "the lattice under open faces is periodic (bc); the faces replace its walls");
+  for (int F = 0; F < 4; ++F) {
+    if (fp->kind[F] < ELBM_FACE_PERIODIC || fp->kind[F] > ELBM_FACE_OUTLET)
+      return fail(ELBM_EINVAL, "face kind out of range");
+    if (fp->kind[F] == ELBM_FACE_PERIODIC && fp->node_kind[F])
+      return fail(ELBM_EINVAL, "a periodic face takes no per-node kinds");
+  }
+  for (int a = 0; a < 2; ++a) {
+    const bool plo = fp->kind[2 * a] == ELBM_FACE_PERIODIC, phi = fp->kind[2 * a + 1] == ELBM_FACE_PERIODIC;
+    if (plo != phi) return fail(ELBM_EINVAL, "a periodic axis is periodic on both faces");
+    P.o[a] = plo ? 0 : 1;
+    P.n[a] = int32_t(h->p.n[a]) - 2 * P.o[a];
+    if (P.o[a] && P.n[a] < 3)
+      return fail(ELBM_EINVAL, "an open axis needs >= 3 fluid nodes (lattice extent = fluid + 2 ghost nodes)");
+  }
+  // kinds per face node
+  std::vector<int> kinds[4];
+  for (int F = 0; F < 4; ++F) {
+    const int m = F < 2 ? P.n[1] : P.n[0];
+    kinds[F].assign(m, fp->kind[F]);
+    if (fp->node_kind[F])
+      for (int t = 0; t < m; ++t) {
+        const int k = fp->node_kind[F][t];
+        if (k < ELBM_FACE_SYMMETRY || k > ELBM_FACE_OUTLET)
+          return fail(ELBM_EINVAL, "per-node face kinds are SYMMETRY, WALL, INLET or OUTLET");
+        kinds[F][t] = k;
+      }
+  }
+  // boundary nodes (fluid coordinates)
+  std::map<std::pair<int, int>, int> index;
+  const int nx = P.n[0], ny = P.n[1];
+  auto on = [&](int F, int x, int y) {
+    if (!P.o[F >> 1]) return false;
+    return (F == 0 && x == 0) || (F == 1 && x == nx - 1) || (F == 2 && y == 0) || (F == 3 && y == ny - 1);
+  };
+  std::vector<FaceNode> corners;
+  for (int F = 0; F < 4; ++F) {
+    if (!P.o[F >> 1]) continue;
+    const int m = F < 2 ? ny : nx;
+    for (int t = 0; t < m; ++t) {
+      const int x = F < 2 ? (F == 0 ? 0 : nx - 1) : t, y = F < 2 ? t : (F == 2 ? 0 : ny - 1);
+      int nf = 0;
+      for (int G = 0; G < 4; ++G) nf += on(G, x, y) ? 1 : 0;
+      if (nf == 1) {
+        index[{x, y}] = int(P.nodes.size());
+        P.nodes.push_back(FaceNode{x, y, F, kinds[F][t]});
+      } else if (F < 2) {
+        const int k = kinds[F][t];
+        if (k != ELBM_FACE_INLET && k != ELBM_FACE_OUTLET)
+          return fail(ELBM_EUNSUPPORTED, "a corner node needs an INLET or OUTLET x face");
+        corners.push_back(FaceNode{x, y, F, k});
+      }
+    }
+  }
+  P.n_single = int32_t(P.nodes.size());
+  for (const FaceNode& c : corners) {
+    index[{c.x, c.y}] = int(P.nodes.size());
+    P.nodes.push_back(c);
+  }
+  P.n_corner = int32_t(corners.size());
+  // ghost ring (storage coordinates)
+  const int NX = int(h->p.n[0]), NY = int(h->p.n[1]);
+  for (int Y = 0; Y < NY; ++Y)
+    for (int X = 0; X < NX; ++X) {
+      const bool gx = P.o[0] && (X == 0 || X == NX - 1), gy = P.o[1] && (Y == 0 || Y == NY - 1);
+      if (!gx && !gy) continue;
+      FaceGhost g{X, Y, -1, 0, 1.0};
+      if (gx != gy) {
+        const int a = gx ? 0 : 1;
+        const int x = X - P.o[0], y = Y - P.o[1];
+        const int fx = gx ? (X == 0 ? 0 : nx - 1) : x, fy = gy ? (Y == 0 ? 0 : ny - 1) : y;
+        const int F = gx ? (X == 0 ? 0 : 1) : (Y == 0 ? 2 : 3);
+        const int t = a == 0 ? fy : fx;
+        g.node = index.at({fx, fy});
+        g.axis = a;
+        g.parity = face_odd(kinds[F][t]) ? -1.0 : 1.0;
+      }
+      P.ghosts.push_back(g);
+    }
+  P.off_nodes = 0;
+  P.off_ghosts = align_up(P.nodes.size() * sizeof(FaceNode), kAlign);
+  P.off_mom = P.off_ghosts + align_up(P.ghosts.size() * sizeof(FaceGhost), kAlign);
+  P.bytes = P.off_mom + align_up(P.nodes.size() * 3 * sizeof(double), kAlign) + kAlign;
+  return ELBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t elbm_faces_query_bytes(elbm_handle lattice, const elbm_faces_params* fp, size_t* bytes) {
+  if (!bytes) return fail(ELBM_EINVAL, "NULL argument");
+  FacePlan P;
+  const int32_t s = plan_faces(lattice, fp, P);
+  if (s) return s;
+  *bytes = P.bytes;
+  return ELBM_OK;
+}
+
+int32_t elbm_faces_create(elbm_handle h, const elbm_faces_params* fp, void* dev_buf, size_t bytes,
+                          elbm_faces_handle* out) {
+  if (!out) return fail(ELBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  FacePlan P;
+  int32_t s = plan_faces(h, fp, P);
+  if (s) return s;
+  if (!dev_buf) return fail(ELBM_EINVAL, "dev_buf is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) return fail(ELBM_EINVAL, "dev_buf must be 256-byte aligned");
+  if (bytes < P.bytes)
+    return fail(ELBM_ENOMEM, "device buffer holds " + std::to_string(bytes) + " bytes, " + std::to_string(P.bytes) +
+                                 " needed");
+  s = set_dev(h->device);
+  if (s) return s;
+  char* base = static_cast<char*>(dev_buf);
+  if (!P.nodes.empty())
+    HIPCHK(hipMemcpyAsync(base + P.off_nodes, P.nodes.data(), P.nodes.size() * sizeof(FaceNode),
+                          hipMemcpyHostToDevice, h->stream));
+  if (!P.ghosts.empty())
+    HIPCHK(hipMemcpyAsync(base + P.off_ghosts, P.ghosts.data(), P.ghosts.size() * sizeof(FaceGhost),
+                          hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  auto* f = new (std::nothrow) elbm_faces_s();
+  if (!f) return fail(ELBM_EINVAL, "out of host memory");
+  f->h = h;
+  FaceArgs& A = f->args;
+  A.pstride = h->pstride;
+  for (int a = 0; a < 2; ++a) {
+    A.N[a] = int32_t(h->p.n[a]);
+    A.o[a] = P.o[a];
+    A.n[a] = P.n[a];
+    A.lam[a] = h->p.lambda[a];
+    A.g[a] = h->p.force[a];
+  }
+  A.T = h->p.T;
+  A.omega = h->p.omega;
+  for (int i = 0; i < 9; ++i) A.w[i] = h->c64.W[0][i % 3] * h->c64.W[1][i / 3];
+  for (int F = 0; F < 4; ++F) {
+    A.wall_u[F] = fp->wall_velocity[F];
+    A.inlet_u[F][0] = fp->inlet_velocity[F][0];
+    A.inlet_u[F][1] = fp->inlet_velocity[F][1];
+  }
+  A.nodes = reinterpret_cast<const FaceNode*>(base + P.off_nodes);
+  A.n_single = P.n_single;
+  A.n_corner = P.n_corner;
+  A.ghosts = reinterpret_cast<const FaceGhost*>(base + P.off_ghosts);
+  A.n_ghost = int32_t(P.ghosts.size());
+  A.mom = reinterpret_cast<double*>(base + P.off_mom);
+  *out = f;
+  return ELBM_OK;
+}
+
+int32_t elbm_faces_step(elbm_faces_handle f, int64_t nsteps) {
+  if (!f) return fail(ELBM_EINVAL, "NULL handle");
+  if (nsteps < 0) return fail(ELBM_EINVAL, "nsteps must be >= 0");
+  elbm_lattice* h = f->h;
+  int32_t s = set_dev(h->device);
+  if (s) return s;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    f->args.h = static_cast<float*>(state_buf(h));
+    HIPCHK(launch_faces(f->args, h->stream));
+    s = elbm_step(h, 1);
+    if (s) return s;
+  }
+  return ELBM_OK;
+}
+
+int32_t elbm_faces_destroy(elbm_faces_handle f) {
+  delete f;
+  return ELBM_OK;
+}
+
+}  // extern "C"

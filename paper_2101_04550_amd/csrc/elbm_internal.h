@@ -144,6 +144,42 @@ hipError_t static_scratch(void** out);
 // bytes travel as kernel arguments: no staging memory).
 hipError_t launch_write_bytes(void* dst, const unsigned char* src, size_t bytes, hipStream_t st);
 
+// ---- open boundaries of a D2Q9 lattice (elbm_faces.hip) ----
+// A fluid boundary node (fluid coordinates) with the face it is on
+// (0: x-, 1: x+, 2: y-, 3: y+) and that face's kind at it (ELBM_FACE_*).
+struct FaceNode {
+  int32_t x, y;
+  int32_t face, kind;
+};
+// A ghost node (storage coordinates), the boundary node whose anomaly it
+// mirrors across the face (index into the node list, -1 for none: corner
+// ghosts), the face's normal axis and the parity of the mirrored normal
+// momentum (-1 at walls and symmetry planes, +1 at inlets and outlets).
+struct FaceGhost {
+  int32_t X, Y;
+  int32_t node, axis;
+  double parity;
+};
+struct FaceArgs {
+  float* h;               // state buffer (FP32 deviations), plane slabs along y
+  int64_t pstride;
+  int32_t N[2];           // storage extents (fluid + ghost ring on open axes)
+  int32_t o[2];           // 1 on an open axis (ghost ring), 0 on a periodic one
+  int32_t n[2];           // fluid extents
+  double lam[2], T, omega, g[2];
+  double w[9];            // reference weights of the deviations
+  double wall_u[4];       // tangential wall velocity per face
+  double inlet_u[4][2];   // inlet velocity per face
+  const FaceNode* nodes;  // n_single boundary nodes on one face, then n_corner corner nodes
+  int32_t n_single, n_corner;
+  const FaceGhost* ghosts;
+  int32_t n_ghost, pad;
+  double* mom;            // 3 doubles per node: pulled rho, j_x, j_y after the fill
+};
+// Rewrites the ghost ring of the state for the next pull (boundary nodes on
+// one face, then corners, then the ghosts' anomaly populations).
+hipError_t launch_faces(const FaceArgs& a, hipStream_t st);
+
 // ---- launchers (defined in the .hip translation units) ----
 // staged: the LDS-staged D3Q27 kernel for 16-bit storage (periodic, full tiles).
 hipError_t launch_step(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,

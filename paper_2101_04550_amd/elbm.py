@@ -88,6 +88,21 @@ class ElbmDiag(C.Structure):
         }
 
 
+FACE_PERIODIC, FACE_SYMMETRY, FACE_WALL, FACE_INLET, FACE_OUTLET = range(5)
+FACE_NAMES = {"periodic": FACE_PERIODIC, "symmetry": FACE_SYMMETRY, "wall": FACE_WALL, "inlet": FACE_INLET,
+              "outlet": FACE_OUTLET}
+
+
+class ElbmFacesParams(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32),
+        ("kind", C.c_int32 * 4),
+        ("node_kind", C.POINTER(C.c_int8) * 4),
+        ("wall_velocity", C.c_double * 4),
+        ("inlet_velocity", (C.c_double * 2) * 4),
+    ]
+
+
 _P = C.POINTER
 _sigs = {
     "elbm_abi_version": (C.c_uint32, []),
@@ -114,6 +129,10 @@ _sigs = {
     "elbm_batch_run": (C.c_int32, [C.c_void_p, _P(C.c_void_p), _P(C.c_int64), C.c_int32, C.c_int32]),
     "elbm_batch_destroy": (C.c_int32, [C.c_void_p]),
     "elbm_batch_run_static": (C.c_int32, [_P(C.c_void_p), _P(C.c_int64), C.c_int32, C.c_void_p]),
+    "elbm_faces_query_bytes": (C.c_int32, [C.c_void_p, _P(ElbmFacesParams), _P(C.c_size_t)]),
+    "elbm_faces_create": (C.c_int32, [C.c_void_p, _P(ElbmFacesParams), C.c_void_p, C.c_size_t, _P(C.c_void_p)]),
+    "elbm_faces_step": (C.c_int32, [C.c_void_p, C.c_int64]),
+    "elbm_faces_destroy": (C.c_int32, [C.c_void_p]),
 }
 STATIC_MAX_LATTICES = 256
 for _name, (_res, _args) in _sigs.items():
@@ -297,6 +316,65 @@ class Lattice:
     def close(self):
         if getattr(self, "handle", None):
             _check(_lib.elbm_destroy(self.handle), "elbm_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _face_kind(k):
+    return FACE_NAMES[k] if isinstance(k, str) else int(k)
+
+
+class Faces:
+    """Open boundaries (elbm_faces_*) of a D2Q9 FP32 lattice that carries a
+    ghost ring on each non-periodic axis (its extents are the fluid extents
+    plus 2 there).
+
+    kinds: four entries (x-, x+, y-, y+), each a kind for the whole face or a
+    sequence with one kind per fluid node along it; wall_velocity: four
+    tangential wall velocities; inlet_velocity: four (u_x, u_y)."""
+
+    def __init__(self, lattice: "Lattice", kinds, wall_velocity=(0.0, 0.0, 0.0, 0.0),
+                 inlet_velocity=((0.0, 0.0),) * 4):
+        import torch
+
+        self.lattice = lattice
+        fp = ElbmFacesParams()
+        fp.abi_version = ABI_VERSION
+        self._arrays = []
+        for F in range(4):
+            k = kinds[F]
+            if isinstance(k, (str, int, np.integer)):
+                fp.kind[F] = _face_kind(k)
+            else:
+                arr = np.ascontiguousarray([_face_kind(v) for v in k], dtype=np.int8)
+                self._arrays.append(arr)
+                fp.kind[F] = int(arr[0])
+                fp.node_kind[F] = arr.ctypes.data_as(C.POINTER(C.c_int8))
+            fp.wall_velocity[F] = float(wall_velocity[F])
+            fp.inlet_velocity[F][0] = float(inlet_velocity[F][0])
+            fp.inlet_velocity[F][1] = float(inlet_velocity[F][1])
+        self.params = fp
+        nb = C.c_size_t(0)
+        _check(_lib.elbm_faces_query_bytes(lattice.handle, C.byref(fp), C.byref(nb)), "elbm_faces_query_bytes")
+        with torch.cuda.device(lattice.device), torch.cuda.stream(lattice.stream):
+            self.buffer = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=lattice.device)
+        h = C.c_void_p()
+        _check(_lib.elbm_faces_create(lattice.handle, C.byref(fp), C.c_void_p(self.buffer.data_ptr()),
+                                      self.buffer.numel(), C.byref(h)), "elbm_faces_create")
+        self.handle = h
+
+    def step(self, nsteps=1):
+        _check(_lib.elbm_faces_step(self.handle, int(nsteps)), "elbm_faces_step")
+        return self
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(_lib.elbm_faces_destroy(self.handle), "elbm_faces_destroy")
             self.handle = None
 
     def __del__(self):
