@@ -39,15 +39,23 @@ the missing ones are set, per the kind of the face the node is on:
     the product form (Sec. 2.2, eq. prod) carries every diagonal second
     moment; the last term adds the off-diagonal one without changing rho,
     j or the diagonal moments.
-* INLET: f_i = f^eq_i(rho(x_f), u_in), the equilibrium (Sec. 2.3, eq. 27eq)
-  at the prescribed velocity and the inward neighbour's density.
-* OUTLET: f_i(x) = f_i(x_f), the pulled population of the inward neighbour
-  (zero gradient).
-u_f and rho(x_f) are the moments of the inward neighbour's post-collision
+* INLET (prescribed velocity u_in at the halfway plane): bounce-back from a
+  surface moving at u_in, f_i = f'_{-i}(x) + f^eq_i(rho_x, u_in) -
+  f^eq_{-i}(rho_x, u_in), with the equilibrium of Sec. 2.3 (eq. 27eq) and
+  rho_x the node's own post-collision density. (Setting the missing
+  populations to an equilibrium at the boundary node instead -- with or
+  without a non-equilibrium part -- lets disturbances grow at the inlet on
+  the lambda_x = 2 lattice at omega = 1.97; this form stays stable.)
+* OUTLET (prescribed density rho_out): the equilibrium at rho_out and the
+  inward neighbour's velocity plus the neighbour's non-equilibrium part,
+  f_i = f^eq_i(rho_out, u_f) + f_i(x_f) - f^eq_i(rho_f, u_f), with f_i(x_f)
+  the neighbour's pulled population. (A plain zero-gradient copy lets the
+  mass drift when a wall displaces the stream.)
+u_f and rho_f are the moments of the inward neighbour's post-collision
 state of the previous step (reported velocity, as ``elbm_oracle.velocity``).
 A corner node (on two non-periodic faces) takes the rule of its x face,
 which must be INLET or OUTLET; it is set after the other boundary nodes, so
-an OUTLET corner copies its neighbour's completed pulled populations.
+an OUTLET corner uses its neighbour's completed pulled populations.
 
 Collision as ``elbm_oracle.collide`` with one change: the central difference
 of the anomaly Q~_a (Sec. 2.3, eq. Paastar1) across a face uses an odd ghost
@@ -82,12 +90,14 @@ class Faces:
     kind[F] is either one int for the whole face F (0: x-, 1: x+, 2: y-,
     3: y+) or a sequence with one kind per face node (n_y for x faces, n_x for
     y faces); wall_velocity[F] is the tangential velocity of WALL nodes of F;
-    inlet_velocity[F] the (u_x, u_y) of its INLET nodes.
+    inlet_velocity[F] the (u_x, u_y) of its INLET nodes; outlet_density[F]
+    the density of its OUTLET nodes.
     """
     n: tuple
     kind: list
     wall_velocity: tuple = (0.0, 0.0, 0.0, 0.0)
     inlet_velocity: tuple = ((0.0, 0.0),) * 4
+    outlet_density: tuple = (1.0, 1.0, 1.0, 1.0)
     node_kind: list = field(init=False)
 
     def __post_init__(self):
@@ -138,6 +148,27 @@ def grad_populations(rho, u, Pi_neq, T, lam, c):
         f[i] = rho * O.psi(int(c[i, 0]), u[0], P[0], lam[0]) * O.psi(int(c[i, 1]), u[1], P[1], lam[1])
         f[i] += c[i, 0] * c[i, 1] * Pi_neq[0][1] / (4.0 * lam[0] * lam[1])
     return f
+
+
+def _inlet(f, fpost, p, fc, F, x, y, M):
+    """Bounce-back from a surface moving at the inlet velocity."""
+    c = p.c
+    Q = c.shape[0]
+    rho_x, _ = _node_state(fpost, p, x, y)
+    feq = O.equilibrium(np.array(rho_x), np.array(fc.inlet_velocity[F], dtype=np.float64), p.T, p.lam, c)
+    for i in M:
+        j = Q - 1 - i
+        f[i, y, x] = fpost[j, y, x] + feq[i] - feq[j]
+
+
+def _outlet(f, fpost, p, fc, F, x, y, xf, M):
+    """Prescribed density, the neighbour's velocity and non-equilibrium part."""
+    c = p.c
+    rho_f, u_f = _node_state(fpost, p, *xf)
+    f_out = O.equilibrium(np.array(float(fc.outlet_density[F])), u_f, p.T, p.lam, c)
+    f_nb = O.equilibrium(np.array(rho_f), u_f, p.T, p.lam, c)
+    for i in M:
+        f[i, y, x] = f_out[i] + f[i, xf[1], xf[0]] - f_nb[i]
 
 
 def stream_open(fpost, p: O.Params, fc: Faces):
@@ -214,13 +245,9 @@ def stream_open(fpost, p: O.Params, fc: Faces):
             for i in M:
                 f[i, y, x] = fg[i]
         elif kind == INLET:
-            rho_f, _ = _node_state(fpost, p, *xf)
-            feq = O.equilibrium(np.array(rho_f), np.array(fc.inlet_velocity[F], dtype=np.float64), p.T, lam, c)
-            for i in M:
-                f[i, y, x] = feq[i]
+            _inlet(f, fpost, p, fc, F, x, y, M)
         elif kind == OUTLET:
-            for i in M:
-                f[i, y, x] = f[i, xf[1], xf[0]]
+            _outlet(f, fpost, p, fc, F, x, y, xf, M)
         else:
             raise ValueError(f"face kind {kind} at a boundary node")
 
@@ -231,13 +258,9 @@ def stream_open(fpost, p: O.Params, fc: Faces):
         xf = (x + s, y)
         M = missing(x, y)
         if kind == INLET:
-            rho_f, _ = _node_state(fpost, p, *xf)
-            feq = O.equilibrium(np.array(rho_f), np.array(fc.inlet_velocity[F], dtype=np.float64), p.T, lam, c)
-            for i in M:
-                f[i, y, x] = feq[i]
+            _inlet(f, fpost, p, fc, F, x, y, M)
         elif kind == OUTLET:
-            for i in M:
-                f[i, y, x] = f[i, xf[1], xf[0]]
+            _outlet(f, fpost, p, fc, F, x, y, xf, M)
         else:
             raise ValueError("a corner node needs an INLET or OUTLET x face")
     return f
