@@ -315,9 +315,10 @@ int32_t elbm_batch_run_static(const elbm_handle* hs, const int64_t* steps, int32
  *                      velocity interpolated through the wall, the density
  *                      of the node's mass and normal-momentum balance and
  *                      the Navier-Stokes stress of the interpolated velocity
- *  ELBM_FACE_INLET     prescribed velocity inlet_velocity[f] (equilibrium at
- *                      the inward neighbour's density)
- *  ELBM_FACE_OUTLET    zero gradient (the inward neighbour's populations)
+ *  ELBM_FACE_INLET     prescribed velocity inlet_velocity[f] at the halfway
+ *                      plane (bounce-back from a surface moving at it)
+ *  ELBM_FACE_OUTLET    prescribed density outlet_density[f], with the inward
+ *                      neighbour's velocity and non-equilibrium part
  * Faces are indexed 0: x-, 1: x+, 2: y-, 3: y+. A corner node (on two
  * non-periodic faces) follows its x face, which must then be INLET or
  * OUTLET. */
@@ -334,13 +335,15 @@ enum {
  *  node_kind[4]    NULL or a host array of one kind per fluid node along
  *                  face f (n_y for x faces, n_x for y faces; read at create)
  *  wall_velocity   tangential velocity of the WALL nodes of face f
- *  inlet_velocity  (u_x, u_y) of the INLET nodes of face f */
+ *  inlet_velocity  (u_x, u_y) of the INLET nodes of face f
+ *  outlet_density  density of the OUTLET nodes of face f (> 0 where used) */
 typedef struct elbm_faces_params {
   uint32_t abi_version;
   int32_t kind[4];
   const int8_t* node_kind[4];
   double wall_velocity[4];
   double inlet_velocity[4][2];
+  double outlet_density[4];
 } elbm_faces_params;
 
 typedef struct elbm_faces_s* elbm_faces_handle;

@@ -1070,6 +1070,15 @@ int32_t plan_faces(const elbm_lattice* h, const elbm_faces_params* fp, FacePlan&
         kinds[F][t] = k;
       }
   }
+  for (int F = 0; F < 4; ++F) {
+    bool outlet = false;
+    for (int k : kinds[F]) outlet = outlet || k == ELBM_FACE_OUTLET;
+    if (outlet && !(fp->outlet_density[F] > 0.0 && std::isfinite(fp->outlet_density[F])))
+      return fail(ELBM_EINVAL, "an OUTLET face needs a positive, finite outlet_density");
+    for (int b = 0; b < 2; ++b)
+      if (!std::isfinite(fp->inlet_velocity[F][b])) return fail(ELBM_EINVAL, "inlet_velocity must be finite");
+    if (!std::isfinite(fp->wall_velocity[F])) return fail(ELBM_EINVAL, "wall_velocity must be finite");
+  }
   // boundary nodes (fluid coordinates)
   std::map<std::pair<int, int>, int> index;
   const int nx = P.n[0], ny = P.n[1];
@@ -1182,6 +1191,7 @@ int32_t elbm_faces_create(elbm_handle h, const elbm_faces_params* fp, void* dev_
     A.wall_u[F] = fp->wall_velocity[F];
     A.inlet_u[F][0] = fp->inlet_velocity[F][0];
     A.inlet_u[F][1] = fp->inlet_velocity[F][1];
+    A.outlet_rho[F] = fp->outlet_density[F];
   }
   A.nodes = reinterpret_cast<const FaceNode*>(base + P.off_nodes);
   A.n_single = P.n_single;

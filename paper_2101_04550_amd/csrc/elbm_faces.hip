@@ -27,8 +27,14 @@
 //            normal-momentum balance rho_t (1 - s u_t,n/lambda_n) =
 //            S_0 + 2 S_out, and the stress rho_t (T + u_t u_t)
 //            - (rho_t T/omega)(grad u_t + grad u_t^T);
-//  INLET     f_i = f^eq_i(rho(x_f), u_in) (Sec. 2.3, eq. 27eq);
-//  OUTLET    f_i = the inward neighbour's pulled f_i.
+//  INLET     f_i = f'_{-i}(x) + f^eq_i(rho_x, u_in) - f^eq_{-i}(rho_x, u_in):
+//            bounce-back from a surface moving at u_in at the halfway plane,
+//            with the equilibrium of Sec. 2.3 (eq. 27eq) at the node's own
+//            density (an equilibrium set at the node itself lets
+//            disturbances grow on the lambda_x = 2 lattice near omega = 2);
+//  OUTLET    f_i = f^eq_i(rho_out, u_f) + f_i(x_f) - f^eq_i(rho_f, u_f): the
+//            prescribed density with the inward neighbour's velocity and
+//            non-equilibrium part.
 // All of it in FP64 from the stored FP32 deviations; a population is written
 // back rounded to FP32 as a deviation from the reference weight.
 #include "elbm.h"
@@ -132,15 +138,28 @@ __device__ void boundary_rule(const View& v, const FaceNode& nd, double (&fm)[9]
               cx * cy * pxy / (4.0 * A.lam[0] * A.lam[1]);
     }
   } else if (kind == ELBM_FACE_INLET) {
-    double rf, uf[2];
-    v.state(xf, yf, rf, uf);
+    double rx, ux0[2];
+    v.state(x, y, rx, ux0);
     const double ux = A.inlet_u[F][0], uy = A.inlet_u[F][1];
     const double Px = A.T + ux * ux, Py = A.T + uy * uy;  // equilibrium pressure (Sec. 2.3, eq. Peqa)
-    for (int i = 0; i < 9; ++i)
-      if (miss[i]) fm[i] = rf * tri(cdir(i, 0), ux, Px, A.lam[0]) * tri(cdir(i, 1), uy, Py, A.lam[1]);
-  } else {  // ELBM_FACE_OUTLET: the inward neighbour's pulled values (complete after the first pass)
-    for (int i = 0; i < 9; ++i)
-      if (miss[i]) fm[i] = v.slot(v.SX(xf) - cdir(i, 0), v.SY(yf) - cdir(i, 1), i);
+    for (int i = 0; i < 9; ++i) {
+      if (!miss[i]) continue;
+      const int cx = cdir(i, 0), cy = cdir(i, 1);
+      const double fe = rx * tri(cx, ux, Px, A.lam[0]) * tri(cy, uy, Py, A.lam[1]);
+      const double fo = rx * tri(-cx, ux, Px, A.lam[0]) * tri(-cy, uy, Py, A.lam[1]);
+      fm[i] = v.slot(v.SX(x), v.SY(y), 8 - i) + fe - fo;
+    }
+  } else {  // ELBM_FACE_OUTLET (the neighbour's pulled values are complete after the first pass)
+    double rf, uf[2];
+    v.state(xf, yf, rf, uf);
+    const double Px = A.T + uf[0] * uf[0], Py = A.T + uf[1] * uf[1];
+    const double ro = A.outlet_rho[F];
+    for (int i = 0; i < 9; ++i) {
+      if (!miss[i]) continue;
+      const int cx = cdir(i, 0), cy = cdir(i, 1);
+      const double e = tri(cx, uf[0], Px, A.lam[0]) * tri(cy, uf[1], Py, A.lam[1]);
+      fm[i] = ro * e + v.slot(v.SX(xf) - cx, v.SY(yf) - cy, i) - rf * e;
+    }
   }
 }
 

@@ -170,6 +170,7 @@ struct FaceArgs {
   double w[9];            // reference weights of the deviations
   double wall_u[4];       // tangential wall velocity per face
   double inlet_u[4][2];   // inlet velocity per face
+  double outlet_rho[4];   // outlet density per face
   const FaceNode* nodes;  // n_single boundary nodes on one face, then n_corner corner nodes
   int32_t n_single, n_corner;
   const FaceGhost* ghosts;

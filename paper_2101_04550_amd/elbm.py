@@ -100,6 +100,7 @@ class ElbmFacesParams(C.Structure):
         ("node_kind", C.POINTER(C.c_int8) * 4),
         ("wall_velocity", C.c_double * 4),
         ("inlet_velocity", (C.c_double * 2) * 4),
+        ("outlet_density", C.c_double * 4),
     ]
 
 
@@ -336,10 +337,11 @@ class Faces:
 
     kinds: four entries (x-, x+, y-, y+), each a kind for the whole face or a
     sequence with one kind per fluid node along it; wall_velocity: four
-    tangential wall velocities; inlet_velocity: four (u_x, u_y)."""
+    tangential wall velocities; inlet_velocity: four (u_x, u_y);
+    outlet_density: four outlet densities."""
 
     def __init__(self, lattice: "Lattice", kinds, wall_velocity=(0.0, 0.0, 0.0, 0.0),
-                 inlet_velocity=((0.0, 0.0),) * 4):
+                 inlet_velocity=((0.0, 0.0),) * 4, outlet_density=(1.0, 1.0, 1.0, 1.0)):
         import torch
 
         self.lattice = lattice
@@ -358,6 +360,7 @@ class Faces:
             fp.wall_velocity[F] = float(wall_velocity[F])
             fp.inlet_velocity[F][0] = float(inlet_velocity[F][0])
             fp.inlet_velocity[F][1] = float(inlet_velocity[F][1])
+            fp.outlet_density[F] = float(outlet_density[F])
         self.params = fp
         nb = C.c_size_t(0)
         _check(_lib.elbm_faces_query_bytes(lattice.handle, C.byref(fp), C.byref(nb)), "elbm_faces_query_bytes")

@@ -387,3 +387,34 @@ def test_enstrophy_of_plane_wave_is_half_discrete_cross_product():
     f = O.init_state(np.ones(s.shape), u, p)
     d = O.diagnostics(f, p)
     assert abs(d.enstrophy / (0.5 * float(np.cross(kd, a) @ np.cross(kd, a))) - 1) < 1e-10
+
+
+def _sheared_stream(lam, T, omega, steps, nx=50, ny=100, U=0.0577, extended=True):
+    """Periodic stream u_x = U (1 + sin(2 pi y / n_y) / 2) with a seeded
+    perturbation of 1e-4; returns max |u_y| / U after `steps` steps."""
+    p = O.Params(n=(nx, ny), lam=lam, T=T, omega=omega, extended=extended)
+    g = np.random.default_rng(1)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    u = np.zeros((2, ny, nx))
+    u[0] = U * (1 + 0.5 * np.sin(2 * np.pi * y / ny))
+    u += 1e-4 * g.standard_normal(u.shape)
+    f = O.equilibrium(1.0 + 1e-4 * g.standard_normal((ny, nx)), u, T, lam, p.c)
+    with np.errstate(all="ignore"):
+        f = O.run(f, p, steps)
+        _, uu = O.velocity(f, p)
+    v = np.abs(uu[1]).max() / U
+    return v if np.isfinite(v) else np.inf
+
+
+def test_stretched_lattice_shear_stability_near_omega_two():
+    """A property of the method that decides the flat-plate resolution: at the
+    viscosity of the Sec. 3.4 plate on its printed 200 x 200 domain
+    (omega = 1.9745, T = 1/3), a sheared periodic stream on lambda_x = 2
+    grows from a 1e-4 perturbation to overflow within 4000 steps, with or
+    without the extended correction, while lambda_x = 1.4 stays at the
+    perturbation's level; at the 4x finer resolution (omega = 1.901) the
+    lambda_x = 2 lattice is stable too."""
+    assert _sheared_stream((2.0, 1.0), 1 / 3, 1.9745, 3000) > 1.0
+    assert _sheared_stream((2.0, 1.0), 1 / 3, 1.9745, 4000, extended=False) > 1.0
+    assert _sheared_stream((1.4, 1.0), 1 / 3, 1.9745, 3000) < 1e-2
+    assert _sheared_stream((2.0, 1.0), 1 / 3, 1.9012, 3000) < 1e-2
