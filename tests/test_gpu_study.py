@@ -24,11 +24,13 @@ above the measured agreement and well inside the control's gap, so a broken
 correction on stretched lattices (sign, spacing, prefactor) fails them.
 This is a property of the method at this resolution, not a parity bound.
 """
+import math
+
 import numpy as np
 import pytest
 
 import inputs as I
-from gpu_helpers import lib
+from gpu_helpers import MEASURED, lib
 
 pytestmark = pytest.mark.gpu
 
@@ -124,3 +126,57 @@ def test_stretched_plate_reproduces_regular(plates):
     ca = np.array(a["cf_edge"])
     cb = np.interp(a["cf_x"], b["cf_x"], b["cf_edge"])
     assert np.abs(ca / cb - 1).max() < 0.05
+
+
+def _hit_run(T, N=256, k0=8.0, ma_t=0.1, re_lambda=72.0, tstar_end=3.0, every=None):
+    """Decaying turbulence of Sec. 3.2 at temperature T: Ma_t = sqrt(<u.u>)/sqrt(T)
+    and Re_lambda fixed, kappa_0 = 2 pi k0 / L = 16 pi / L. Returns t* and the
+    FP64 records (KE, enstrophy) of the sample steps."""
+    E = lib()
+    urms = ma_t * math.sqrt(T) / math.sqrt(3.0)
+    fld = I.hit_field(N, k0=k0, urms=urms, seed_offset=5)
+    lam_T = 2.0 / (2.0 * math.pi * k0 / N)  # Taylor microscale of the k^4 exp(-2 (k/k0)^2) spectrum (R16)
+    nu = urms * lam_T / re_lambda
+    omega = 1.0 / (nu / T + 0.5)
+    L_I = math.sqrt(2.0 * math.pi) / (2.0 * math.pi * k0 / N)
+    tau = L_I / urms
+    steps = int(round(tstar_end * tau))
+    every = every or max(1, int(round(0.05 * tau)))
+    lat = E.Lattice(E.make_params((N, N, N), T=T, omega=omega, diag_every=every,
+                                  diag_capacity=steps // every + 1))
+    lat.init(fld.rho, fld.u)
+    lat.step(steps)
+    hist = lat.diag_history()
+    lat.close()
+    t = np.array([h["step"] / tau for h in hist])
+    ke = np.array([h["ke"] for h in hist])
+    Z = np.array([h["enstrophy"] for h in hist])
+    # u_rms^2 = 2 KE / 3; isotropy: <(d_x u_x)^2> = <|curl u|^2> / 15
+    u2 = 2.0 * ke / 3.0
+    re_l = u2 * np.sqrt(15.0 / Z) / nu
+    ke0 = 1.5 * urms ** 2
+    return dict(t=t, ke=ke / ke0, re_lambda=re_l, steps=steps, omega=omega)
+
+
+@pytest.fixture(scope="module")
+def hit_temperatures():
+    return {T: _hit_run(T) for T in (1.0 / 3.0, 0.55)}
+
+
+def test_hit_temperature_independence(hit_temperatures):
+    """Sec. 3.2: decaying turbulence at Ma_t = 0.1, Re_lambda = 72 gives the
+    same kinetic-energy and Re_lambda histories in eddy-turnover time at
+    T = 1/3 and T = 0.55, the higher temperature in sqrt(0.55 / (1/3)) = 1.28x
+    fewer steps."""
+    a, b = hit_temperatures[1.0 / 3.0], hit_temperatures[0.55]
+    assert a["steps"] / b["steps"] == pytest.approx(math.sqrt(0.55 * 3.0), rel=5e-3)
+    t = np.linspace(0.2, 2.8, 27)
+    ka, kb = np.interp(t, a["t"], a["ke"]), np.interp(t, b["t"], b["ke"])
+    ra, rb = np.interp(t, a["t"], a["re_lambda"]), np.interp(t, b["t"], b["re_lambda"])
+    dk, dr = float(np.abs(ka / kb - 1).max()), float(np.abs(ra / rb - 1).max())
+    MEASURED.append(dict(test="hit_temperature", case="256^3 Ma_t 0.1 Re_lambda 72, t* 0.2-2.8", storage="f32",
+                         component="KE / Re_lambda max rel diff", measured=[dk, dr, float(ka[-1]), float(ra[0])],
+                         target=None, bound=[0.02, 0.03]))
+    assert ka[-1] < 0.6  # the turbulence decays over the run
+    assert dk < 0.02, dk
+    assert dr < 0.03, dr
