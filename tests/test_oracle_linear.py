@@ -36,11 +36,13 @@ def _dpsi_dP(c, lam):
     return -1.0 / lam ** 2 if c == 0 else 0.5 / lam ** 2
 
 
-def step_matrix(k, U, T, omega, lam, extended=True):
+def step_matrix(k, U, T, omega, lam, extended=True, omega_bulk=None):
     """One-step operator on the Fourier amplitudes delta_i of the post-collision
     populations f'_i = F_i + delta_i exp(i k.x) about the uniform state rho = 1,
     u = U (D2Q9; node coordinates x_a = n_a lam_a): pull streaming, then the
-    collision."""
+    collision. With omega_bulk the isotropic part of the pressure correction
+    takes the factor (2 - omega_bulk) / (2 omega_bulk) (the multi-relaxation-
+    time reading of oracle/elbm_mrt.py); the collision part stays LBGK."""
     c = O.velocity_set(2)
     Q = c.shape[0]
     Pb = [T + U[a] ** 2 for a in range(2)]
@@ -52,6 +54,7 @@ def step_matrix(k, U, T, omega, lam, extended=True):
     # drho, dj -> du, dP* (per axis)
     du = np.zeros((2, 3), dtype=complex)
     dP = np.zeros((2, 3), dtype=complex)
+    dG = np.zeros((2, 3), dtype=complex)  # central differences of the anomaly
     for a in range(2):
         du[a, 0] = -U[a]
         du[a, 1 + a] = 1.0
@@ -62,7 +65,11 @@ def step_matrix(k, U, T, omega, lam, extended=True):
             dQ[1 + a] = lam[a] ** 2 - 3.0 * T - 3.0 * U[a] ** 2
             dQ[0] = 2.0 * U[a] ** 3
             grad = 1j * math.sin(k[a] * lam[a]) / lam[a]  # central difference of exp(i k x)
-            dP[a] = dP[a] + (2.0 - omega) / (2.0 * omega) * grad * dQ
+            dG[a] = grad * dQ
+    ob = omega if omega_bulk is None else omega_bulk
+    iso = 0.5 * (dG[0] + dG[1])
+    for a in range(2):
+        dP[a] = dP[a] + (2.0 - omega) / (2.0 * omega) * (dG[a] - iso) + (2.0 - ob) / (2.0 * ob) * iso
     J = np.zeros((Q, Q), dtype=complex)
     for i in range(Q):
         cx, cy = int(c[i, 0]), int(c[i, 1])
