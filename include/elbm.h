@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define ELBM_ABI_VERSION 1u
+#define ELBM_ABI_VERSION 2u
 
 typedef enum elbm_status {
   ELBM_OK = 0,
@@ -50,6 +50,8 @@ typedef enum elbm_status {
 } elbm_status;
 
 enum { ELBM_BC_PERIODIC = 0, ELBM_BC_BOUNCEBACK = 1 };
+
+enum { ELBM_COLLISION_BGK = 0, ELBM_COLLISION_MRT = 1 };
 
 /* Storage of the populations in device memory. The kernels always compute
  * in FP32 on deviations h_i = f_i - w_i from the reference equilibrium
@@ -87,6 +89,17 @@ enum { ELBM_STORE_F32 = 0, ELBM_STORE_F16 = 1, ELBM_STORE_BF16 = 2 };
  *  mode_k[3]    physical wave vector k of the measured plane mode, and
  *  mode_dir[3]  the velocity direction d whose amplitude
  *               < (d.u) exp(-i k.x) > the diagnostics report (Sec. 3.1).
+ *  collision    ELBM_COLLISION_BGK (Sec. 2.1, eq. LBGK) or ELBM_COLLISION_MRT
+ *               (D2Q9 only; the multi-relaxation-time extension that Sec. 4
+ *               names): the deviatoric non-equilibrium stress relaxes at
+ *               omega, its trace at omega_bulk, the non-equilibrium part
+ *               above second order at omega_ghost (the stress parts mapped
+ *               back by the linear Grad map of the product-form lattice),
+ *               and the pressure correction of Sec. 2.4 takes the bulk
+ *               rate's factor (2 - omega_bulk)/(2 omega_bulk) on its
+ *               isotropic part. Shear viscosity nu = (1/omega - 1/2) T;
+ *               sound decays by (nu + (1/omega_bulk - 1/2) T) k^2 / 2.
+ *  omega_bulk, omega_ghost  in (0, 2) when collision is MRT, else unused.
  */
 typedef struct elbm_params {
   uint32_t abi_version;
@@ -102,9 +115,11 @@ typedef struct elbm_params {
   int32_t extended;
   int32_t diag_every;
   int32_t diag_capacity;
-  int32_t reserved0;
+  int32_t collision;
   double mode_k[3];
   double mode_dir[3];
+  double omega_bulk;
+  double omega_ghost;
 } elbm_params;
 
 /* Global diagnostics of the post-collision state after `step` steps, reduced
@@ -284,7 +299,7 @@ int32_t elbm_batch_destroy(elbm_batch b);
  * lattice hs[k] by steps[k] >= 0 steps exactly as elbm_batch_run (same
  * kernels, same results bitwise), with no batch object: the per-class
  * descriptor tables live in a fixed device array that the library holds on
- * every device it runs on until the process ends (1024 + 304 *
+ * every device it runs on until the process ends (1024 + 336 *
  * ELBM_STATIC_MAX_LATTICES bytes); they are written by small kernels whose
  * arguments carry the bytes. Nothing is allocated and no graph is captured.
  *  hs, steps   count lattices (all on the current device, none twice) and
@@ -349,7 +364,8 @@ typedef struct elbm_faces_params {
 typedef struct elbm_faces_s* elbm_faces_handle;
 
 /* Device bytes of the face tables of `lattice` (node lists, ghost list,
- * per-node moments). The lattice must be D2Q9 with FP32 storage, u_adv = 0
+ * per-node moments). The lattice must be D2Q9 with FP32 storage, the LBGK
+ * collision, u_adv = 0
  * and both axes periodic (bc), and it must carry the ghost ring: its
  * extents are the fluid extents plus 2 along every axis whose faces are not
  * PERIODIC (fluid extents >= 3 there). ELBM_EINVAL / ELBM_EUNSUPPORTED with

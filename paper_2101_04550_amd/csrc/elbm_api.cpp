@@ -195,6 +195,13 @@ int32_t check(const elbm_params* p) {
   if (p->storage < ELBM_STORE_F32 || p->storage > ELBM_STORE_BF16)
     return fail(ELBM_EINVAL, "storage must be ELBM_STORE_F32, ELBM_STORE_F16 or ELBM_STORE_BF16");
   if (p->extended != 0 && p->extended != 1) return fail(ELBM_EINVAL, "extended must be 0 or 1");
+  if (p->collision != ELBM_COLLISION_BGK && p->collision != ELBM_COLLISION_MRT)
+    return fail(ELBM_EINVAL, "collision must be ELBM_COLLISION_BGK or ELBM_COLLISION_MRT");
+  if (p->collision == ELBM_COLLISION_MRT) {
+    if (p->lattice != 9) return fail(ELBM_EUNSUPPORTED, "the MRT collision is implemented for D2Q9 lattices only");
+    if (!(p->omega_bulk > 0.0 && p->omega_bulk < 2.0) || !(p->omega_ghost > 0.0 && p->omega_ghost < 2.0))
+      return fail(ELBM_EINVAL, "omega_bulk and omega_ghost must lie in (0, 2)");
+  }
   if (p->diag_every < 0) return fail(ELBM_EINVAL, "diag_every must be >= 0");
   if (p->diag_every > 0 && (p->diag_capacity < 1 || p->diag_capacity > (1 << 24)))
     return fail(ELBM_EINVAL, "diag_capacity must lie in [1, 2^24] when diag_every > 0");
@@ -303,6 +310,13 @@ void fill_desc(elbm_lattice* h) {
   const double scale = p.storage == ELBM_STORE_F16 ? double(kF16Scale) : 1.0;
   d.om1 = float(1.0 - p.omega);
   d.oms = float(p.omega * scale);
+  d.mrt = p.collision == ELBM_COLLISION_MRT ? 1 : 0;
+  if (d.mrt) {
+    d.om1g = float(1.0 - p.omega_ghost);
+    d.cdev = float(p.omega_ghost - p.omega);
+    d.ciso = float(p.omega_ghost - p.omega_bulk);
+    d.coefb = p.extended ? float((2.0 - p.omega_bulk) / (2.0 * p.omega_bulk)) : 0.f;
+  }
   d.scale = float(scale);
   d.inv_scale = float(1.0 / scale);
   d.buf[0] = h->buf[0];
@@ -430,7 +444,9 @@ bool same_problem(const elbm_params& a, const elbm_params& b) {
   return a.lattice == b.lattice && a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2] &&
          std::memcmp(a.lambda, b.lambda, sizeof a.lambda) == 0 && a.T == b.T && a.omega == b.omega &&
          std::memcmp(a.u_adv, b.u_adv, sizeof a.u_adv) == 0 && std::memcmp(a.force, b.force, sizeof a.force) == 0 &&
-         std::memcmp(a.bc, b.bc, sizeof a.bc) == 0 && a.storage == b.storage && a.extended == b.extended;
+         std::memcmp(a.bc, b.bc, sizeof a.bc) == 0 && a.storage == b.storage && a.extended == b.extended &&
+         a.collision == b.collision &&
+         (a.collision == ELBM_COLLISION_BGK || (a.omega_bulk == b.omega_bulk && a.omega_ghost == b.omega_ghost));
 }
 
 }  // namespace
@@ -1039,6 +1055,8 @@ int32_t plan_faces(const elbm_lattice* h, const elbm_faces_params* fp, FacePlan&
   if (fp->abi_version != ELBM_ABI_VERSION) return fail(ELBM_EINVAL, "faces abi_version mismatch");
   if (h->D != 2) return fail(ELBM_EUNSUPPORTED, "open faces are implemented for D2Q9 lattices only");
   if (h->p.storage != ELBM_STORE_F32) return fail(ELBM_EUNSUPPORTED, "open faces need FP32 storage");
+  if (h->p.collision != ELBM_COLLISION_BGK)
+    return fail(ELBM_EUNSUPPORTED, "open faces need the LBGK collision (their Grad rule relaxes at one rate)");
   if (h->p.u_adv[0] != 0.0 || h->p.u_adv[1] != 0.0)
     return fail(ELBM_EUNSUPPORTED, "open faces need u_adv == 0 (rest reference)");
   if (h->p.bc[0] != ELBM_BC_PERIODIC || h->p.bc[1] != ELBM_BC_PERIODIC)

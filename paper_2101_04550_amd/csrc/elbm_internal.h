@@ -78,7 +78,12 @@ struct alignas(16) LatticeDesc {
   float oms;               // omega * scale
   float inv_scale;         // stored value * inv_scale = deviation
   float scale;
-  float pad1;
+  int32_t mrt;             // D2Q9 multi-relaxation-time collision
+  float om1g;              // 1 - omega_ghost
+  float cdev;              // omega_ghost - omega
+  float ciso;              // omega_ghost - omega_bulk
+  float coefb;             // (2 - omega_bulk)/(2 omega_bulk); 0 for the uncorrected control
+  float pad1[3];
 };
 
 struct TableHeader {
@@ -135,6 +140,7 @@ constexpr int kStaticMaxLattices = 256;   // lattices per elbm_batch_run_static 
 constexpr int kStaticClasses = 48;        // kernel classes (one table each)
 constexpr size_t kStaticHeaderBytes = 1024;  // kStaticClasses TableHeaders, padded
 constexpr size_t kStaticScratchBytes = kStaticHeaderBytes + size_t(kStaticMaxLattices) * sizeof(LatticeDesc);
+static_assert(sizeof(LatticeDesc) == 336, "the static scratch size the header documents (1024 + 336 per lattice)");
 static_assert(kStaticClasses * sizeof(TableHeader) <= kStaticHeaderBytes, "table headers fit");
 static_assert(kStaticHeaderBytes % alignof(LatticeDesc) == 0, "descriptors stay aligned");
 // Device address of the fixed scratch array on the current device (looked up

@@ -170,6 +170,8 @@ struct TileConst {
   float lam[3], inv_lam[3], inv_lam2[3], hil[3], mfac[3], anom[3], uref[3], g[3];
   float W[3][3], WW[3][3];
   float omega, coef, inv_scale, scale, om1, oms;
+  bool mrt;
+  float om1g, cdev, ciso, coefb;
 };
 
 // Pulled populations of one node in storage format (FP32 value, or the raw
@@ -352,6 +354,11 @@ __device__ __forceinline__ void load_const(const LatticeDesc* __restrict__ Ld, u
   k.scale = Ld->scale;
   k.om1 = Ld->om1;
   k.oms = Ld->oms;
+  k.mrt = Ld->mrt != 0;
+  k.om1g = Ld->om1g;
+  k.cdev = Ld->cdev;
+  k.ciso = Ld->ciso;
+  k.coefb = Ld->coefb;
 }
 
 // Collision of one node (Sec. 2.1, eq. LBGK; Sec. 2.2-2.4): from the
@@ -380,6 +387,10 @@ __device__ __forceinline__ void collide(const TileConst& k, float drho, const fl
   const float rho = 1.f + drho;
   const float ir = recip(rho);
   float du[3], dP[3], d[3][3], p[3][3];
+  // D2Q9 multi-relaxation-time collision: the isotropic part of the
+  // anomaly difference takes the bulk rate's factor (internal axes 0, 2)
+  const bool mrt = D == 2 && k.mrt;
+  const float giso = mrt ? 0.5f * (Gd[0] + Gd[2]) : 0.f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (D == 2 && a == 1) {
@@ -389,7 +400,8 @@ __device__ __forceinline__ void collide(const TileConst& k, float drho, const fl
       const float x = dj[a] - drho * k.uref[a];
       du[a] = ACC ? __builtin_fmaf(-(x * drho), ir, x) : x * ir;
       const float u = k.uref[a] + du[a];
-      dP[a] = du[a] * (u + k.uref[a]) + k.coef * Gd[a] * ir;
+      const float corr = mrt ? k.coef * (Gd[a] - giso) + k.coefb * giso : k.coef * Gd[a];
+      dP[a] = du[a] * (u + k.uref[a]) + corr * ir;
     }
     const float t1v = du[a] * k.inv_lam[a];
     const float t2v = dP[a] * k.inv_lam2[a];
@@ -459,6 +471,52 @@ __device__ __forceinline__ void collide(const TileConst& k, float drho, const fl
       sx[c] = sr * pe[0][c];
       ex[c] = sr * e[0][c];
       qz[c] = pe[2][c] + e[2][c];
+    }
+  }
+  if constexpr (D == 2) {
+    if (mrt) {
+      // Multi-relaxation-time relaxation in storage scale: fe_i = scale
+      // (f*_i - w_i), n_i = h_i - fe_i; the non-equilibrium stress (physical
+      // x = internal 0, y = internal 2) relaxes at omega (deviator) and
+      // omega_bulk (trace), the rest at omega_ghost:
+      //   o_i = fe_i + (1 - og) n_i + (og - o) G_i(Pi_dev) + (og - ob) G_i(Pi_iso),
+      // G the linear Grad map at the collision's triplets p (dPsi/dP = -1/lam^2
+      // at c = 0, 1/(2 lam^2) at c = +-1; c_x c_y Pi_xy / (4 lam_x lam_y)).
+      const float sc = k.scale, scr = sc * drho;
+      // two passes that recompute fe_i rather than hold it (register budget
+      // of the LBGK path, which shares this kernel)
+      auto feq = [&](int cx, int cy) {
+        return (scr * p[0][cx + 1] + sc * d[0][cx + 1]) * p[2][cy + 1] + k.W[0][cx + 1] * (sc * d[2][cy + 1]);
+      };
+      float pxx = 0.f, pyy = 0.f, pxy = 0.f;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int cx = cq<2>(i, 0), cy = cq<2>(i, 2);
+        const float nq = hval(i) - feq(cx, cy);
+        if (cx != 0) pxx += nq;
+        if (cy != 0) pyy += nq;
+        if (cx * cy > 0) pxy += nq;
+        if (cx * cy < 0) pxy -= nq;
+      }
+      pxx *= k.lam[0] * k.lam[0];
+      pyy *= k.lam[2] * k.lam[2];
+      const float dev = 0.5f * (pxx - pyy), iso = 0.5f * (pxx + pyy);
+      const float qxy = pxy * 0.25f;  // lam_x lam_y Pi_xy-sum / (4 lam_x lam_y)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int cx = cq<2>(i, 0), cy = cq<2>(i, 2);
+        const float fe = feq(cx, cy);
+        const float nq = hval(i) - fe;
+        const float gx = cx == 0 ? -k.inv_lam2[0] : 0.5f * k.inv_lam2[0];
+        const float gy = cy == 0 ? -k.inv_lam2[2] : 0.5f * k.inv_lam2[2];
+        const float px = p[0][cx + 1], py = p[2][cy + 1];
+        const float gdev = (gx * py - px * gy) * dev + float(cx * cy) * qxy;
+        const float gis = (gx * py + px * gy) * iso;
+        float o = fe + k.om1g * nq + k.cdev * gdev + k.ciso * gis;
+        if (FORCE) o += ex[cx + 1] * qz[cy + 1] + sx[cx + 1] * e[2][cy + 1];
+        emit(i, o);
+      }
+      return;
     }
   }
 #pragma unroll

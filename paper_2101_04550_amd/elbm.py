@@ -28,9 +28,10 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, EUNSTABLE = range(6)
 BC_PERIODIC, BC_BOUNCEBACK = 0, 1
+COLLISION_BGK, COLLISION_MRT = 0, 1
 STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 STORAGE_NAMES = {"f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
 
@@ -50,9 +51,11 @@ class ElbmParams(C.Structure):
         ("extended", C.c_int32),
         ("diag_every", C.c_int32),
         ("diag_capacity", C.c_int32),
-        ("reserved0", C.c_int32),
+        ("collision", C.c_int32),
         ("mode_k", C.c_double * 3),
         ("mode_dir", C.c_double * 3),
+        ("omega_bulk", C.c_double),
+        ("omega_ghost", C.c_double),
     ]
 
 
@@ -167,8 +170,11 @@ def _check(status, where):
 
 
 def make_params(n, lam=None, T=1.0 / 3.0, omega=1.0, u_adv=None, force=None, walls=None,
-                storage="f32", extended=True, diag_every=0, diag_capacity=0, mode_k=None, mode_dir=None):
-    """elbm_params from Python values. ``n`` has 2 (D2Q9) or 3 (D3Q27) extents."""
+                storage="f32", extended=True, diag_every=0, diag_capacity=0, mode_k=None, mode_dir=None,
+                omega_bulk=None, omega_ghost=None):
+    """elbm_params from Python values. ``n`` has 2 (D2Q9) or 3 (D3Q27) extents.
+    Giving omega_bulk or omega_ghost selects the multi-relaxation-time
+    collision (the other rate defaults to omega)."""
     D = len(n)
     if D not in (2, 3):
         raise ValueError("n must have 2 or 3 extents")
@@ -191,6 +197,10 @@ def make_params(n, lam=None, T=1.0 / 3.0, omega=1.0, u_adv=None, force=None, wal
     p.extended = 1 if extended else 0
     p.diag_every = int(diag_every)
     p.diag_capacity = int(diag_capacity)
+    mrt = omega_bulk is not None or omega_ghost is not None
+    p.collision = COLLISION_MRT if mrt else COLLISION_BGK
+    p.omega_bulk = float(omega_bulk) if omega_bulk is not None else float(omega)
+    p.omega_ghost = float(omega_ghost) if omega_ghost is not None else float(omega)
     return p
 
 

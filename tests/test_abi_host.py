@@ -57,6 +57,26 @@ def test_walls_with_advection_reference_are_unsupported(D):
     assert E.validate(E.make_params(n, T=0.5, omega=1.5, u_adv=(0.05,) + (0.0,) * (D - 1))) == E.OK
 
 
+def test_mrt_collision_validation():
+    """The multi-relaxation-time collision: D2Q9 only, rates in (0, 2), and a
+    collision code the library knows."""
+    assert E.validate(E.make_params((32, 16), T=0.5, omega=1.6, omega_bulk=1.1, omega_ghost=1.3)) == E.OK
+    p3 = E.make_params((8, 8, 8), T=0.5, omega=1.6, omega_bulk=1.1)
+    assert E.validate(p3) == E.EUNSUPPORTED
+    assert "D2Q9" in E._lib.elbm_last_error().decode()
+    for ob, og in ((0.0, 1.0), (1.0, 2.0), (-0.5, 1.0), (1.0, float("nan"))):
+        assert E.validate(E.make_params((32, 16), T=0.5, omega=1.6, omega_bulk=ob, omega_ghost=og)) == E.EINVAL
+        assert "omega_bulk" in E._lib.elbm_last_error().decode()
+    p = E.make_params((32, 16), T=0.5, omega=1.6)
+    p.collision = 7
+    assert E.validate(p) == E.EINVAL
+    # the LBGK default leaves both extra rates unused
+    p = E.make_params((32, 16), T=0.5, omega=1.6)
+    assert p.collision == E.COLLISION_BGK
+    p.omega_bulk = 5.0
+    assert E.validate(p) == E.OK
+
+
 def test_validation_rejects_bad_lattice_shapes():
     p = E.make_params((8, 8, 8), T=0.5, omega=1.0)
     p.lattice = 15

@@ -132,3 +132,23 @@ def test_long_waves_shear_and_sound(lam, T, ob, og):
     assert len(sound) == 2
     for m in sound:
         assert -math.log(abs(w[m])) / (0.5 * (nu + nub) * k[0] ** 2) == pytest.approx(1.0, abs=1e-4)
+
+
+def _max_growth_at_rest(T, omega, lam, ob, og, nk=25):
+    worst = 0.0
+    for kx in np.linspace(0.0, math.pi / lam[0], nk):
+        for ky in np.linspace(-math.pi / lam[1], math.pi / lam[1], 2 * nk - 1):
+            M = mrt_step_matrix((kx, ky), (0.0, 0.0), T, omega, lam, ob, og)
+            worst = max(worst, float(np.abs(np.linalg.eigvals(M)).max()))
+    return worst
+
+
+def test_linear_stability_at_rest():
+    """The linearised MRT step at rest: no growing mode at the rates of the
+    GPU parity cases on the stretched lattice (omega = 1.6), nor at omega =
+    1.9745 on the regular lattice; but on lambda = (2, 1) at omega = 1.9745
+    with omega_bulk = 1.2, omega_ghost = 1.5 a mode grows by 0.37% per step
+    (k = (pi/2, +-1.37)): the stretching, not the rates alone, makes it."""
+    assert _max_growth_at_rest(0.5, 1.6, (2.0, 1.0), 1.1, 1.3) < 1.0 + 1e-9
+    assert _max_growth_at_rest(1 / 3, 1.9745, (1.0, 1.0), 1.2, 1.5) < 1.0 + 1e-9
+    assert _max_growth_at_rest(1 / 3, 1.9745, (2.0, 1.0), 1.2, 1.5) > 1.003
