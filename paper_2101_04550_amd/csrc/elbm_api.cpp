@@ -310,6 +310,7 @@ void fill_desc(elbm_lattice* h) {
   const double scale = p.storage == ELBM_STORE_F16 ? double(kF16Scale) : 1.0;
   d.om1 = float(1.0 - p.omega);
   d.oms = float(p.omega * scale);
+  d.one = 1.f;
   d.mrt = p.collision == ELBM_COLLISION_MRT ? 1 : 0;
   if (d.mrt) {
     d.om1g = float(1.0 - p.omega_ghost);

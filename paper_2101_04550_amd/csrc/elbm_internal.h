@@ -83,7 +83,8 @@ struct alignas(16) LatticeDesc {
   float cdev;              // omega_ghost - omega
   float ciso;              // omega_ghost - omega_bulk
   float coefb;             // (2 - omega_bulk)/(2 omega_bulk); 0 for the uncorrected control
-  float pad1[3];
+  float one;               // 1.0, read at run time (see Puller::line_moments)
+  float pad1[2];
 };
 
 struct TableHeader {

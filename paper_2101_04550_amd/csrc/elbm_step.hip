@@ -169,7 +169,7 @@ struct TileConst {
   bool w0, w1, w2;
   float lam[3], inv_lam[3], inv_lam2[3], hil[3], mfac[3], anom[3], uref[3], g[3];
   float W[3][3], WW[3][3];
-  float omega, coef, inv_scale, scale, om1, oms;
+  float omega, coef, inv_scale, scale, om1, oms, one;
   bool mrt;
   float om1g, cdev, ciso, coefb;
 };
@@ -266,7 +266,7 @@ struct Puller {
 #pragma unroll
     for (int i = 0; i < Q; ++i) v[i] = h.get(i);
     float r, m[3];
-    line_moments(v, r, m);
+    line_moments(v, S == 1 ? k.one : 1.f, r, m);
     // values are in storage scale: the factors carry 1/scale
     drho = r * k.inv_scale;
     dj[0] = k.mfac[0] * m[0];
@@ -276,7 +276,11 @@ struct Puller {
 
   // Moments of the 3^D values in lattice order: sums along x-lines of three
   // first, then combined (fewer additions than direction by direction).
-  __device__ static __forceinline__ void line_moments(const float (&v)[Q], float& r, float (&m)[3]) {
+  // The x-line sums are written as FMAs by `one` (1.0): with FP16 storage the
+  // caller passes a 1.0 the compiler cannot see, so each FMA takes its 16-bit
+  // operands directly (mixed-precision FMA) instead of converting every value
+  // first; a + 1.0 b rounds exactly as a + b, so the sums are unchanged.
+  __device__ static __forceinline__ void line_moments(const float (&v)[Q], float one, float& r, float (&m)[3]) {
     if (D == 3) {
       float s[3][3], jx = 0.f;
 #pragma unroll
@@ -284,8 +288,8 @@ struct Puller {
 #pragma unroll
         for (int k1 = 0; k1 < 3; ++k1) {
           const int b = 3 * k1 + 9 * k2;
-          s[k1][k2] = (v[b] + v[b + 1]) + v[b + 2];
-          jx += v[b + 2] - v[b];
+          s[k1][k2] = __builtin_fmaf(v[b + 2], one, __builtin_fmaf(v[b], one, v[b + 1]));
+          jx += __builtin_fmaf(v[b], -one, v[b + 2]);
         }
       float rr = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
@@ -303,8 +307,8 @@ struct Puller {
 #pragma unroll
       for (int k2 = 0; k2 < 3; ++k2) {
         const int b = 3 * k2;
-        s[k2] = (v[b] + v[b + 1]) + v[b + 2];
-        jx += v[b + 2] - v[b];
+        s[k2] = __builtin_fmaf(v[b + 2], one, __builtin_fmaf(v[b], one, v[b + 1]));
+        jx += __builtin_fmaf(v[b], -one, v[b + 2]);
       }
       r = (s[0] + s[1]) + s[2];
       m[0] = jx;
@@ -354,6 +358,7 @@ __device__ __forceinline__ void load_const(const LatticeDesc* __restrict__ Ld, u
   k.scale = Ld->scale;
   k.om1 = Ld->om1;
   k.oms = Ld->oms;
+  k.one = Ld->one;
   k.mrt = Ld->mrt != 0;
   k.om1g = Ld->om1g;
   k.cdev = Ld->cdev;
@@ -1169,7 +1174,7 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = Store<S>::to_float(v[i]);
     float r, m[3];
-    Puller<3, S, false>::line_moments(f, r, m);
+    Puller<3, S, false>::line_moments(f, S == 1 ? k.one : 1.f, r, m);
     dr = r * k.inv_scale;
     djo[0] = k.mfac[0] * m[0];
     djo[1] = k.mfac[1] * m[1];
