@@ -68,6 +68,9 @@ def parse_args():
     ap.add_argument("--no-ceiling", action="store_true", help="omit the bandwidth-ceiling probe")
     ap.add_argument("--ceiling-only", action="store_true",
                     help="only the bandwidth-ceiling probe, one JSON line: for its kernel profile")
+    ap.add_argument("--mrt-only", action="store_true",
+                    help="only the multi-relaxation-time collision against LBGK (D3Q27 256^3, D2Q9 4096^2), "
+                         "one JSON line")
     ap.add_argument("--hit-only", action="store_true",
                     help="only the 256^3 turbulence legs (no D2Q9 or serving leg): for per-kernel profiles")
     return ap.parse_args()
@@ -349,6 +352,54 @@ def channel_leg(steps=300):
     return out
 
 
+def mrt_leg(steps=200):
+    """Step time of the multi-relaxation-time collision (omega_bulk = 1.2,
+    omega_ghost = 1.0) beside LBGK on the same lattice: D3Q27 256^3
+    turbulence (T = 0.5) in FP32 / FP16 / BF16 and the D2Q9 4096^2 double
+    shear layer (T = 0.5, omega = 1.9) in FP32 / FP16; HIP events over
+    `steps` steps after 30 warm-up steps, no sample steps."""
+    import torch
+
+    import inputs as I
+    from paper_2101_04550_amd import elbm as E
+
+    def one(params, fld):
+        lat = E.Lattice(params)
+        lat.init(fld.rho, fld.u)
+        lat.step(30)
+        lat.sync()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(lat.stream)
+        lat.step(steps)
+        b.record(lat.stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / steps
+        kern = lat.kernel_info()["kernel"]
+        N = lat.N
+        lat.close()
+        return {"ms": round(ms, 5), "mlups": round(N / (ms * 1e-3) / 1e6, 1), "kernel": kern}
+
+    rates = dict(omega_bulk=1.2, omega_ghost=1.0)
+    out = {}
+    fld = I.hit_field(N_HIT, k0=4.0, urms=0.05)
+    for st in ("f32", "f16", "bf16"):
+        base = dict(T=0.5, omega=OMEGA_HIT, storage=st)
+        out[f"d3q27_{N_HIT}_{st}"] = {
+            "lbgk": one(E.make_params((N_HIT,) * 3, **base), fld),
+            "mrt": one(E.make_params((N_HIT,) * 3, **base, **rates), fld)}
+    del fld
+    torch.cuda.empty_cache()
+    n2 = (4096, 4096)
+    fld = I.double_shear_layer(n2)
+    for st in ("f32", "f16"):
+        base = dict(T=0.5, omega=1.9, storage=st)
+        out[f"d2q9_4096_{st}"] = {"lbgk": one(E.make_params(n2, **base), fld),
+                                  "mrt": one(E.make_params(n2, **base, **rates), fld)}
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(seconds_budget=20.0):
     """The FP64 NumPy oracle (untuned) on a bounded sample of the same workload:
     a 96^3 box of the same spectrum (k0 = 4), timed over whole steps, on one
@@ -409,6 +460,9 @@ def main():
         return
     if args.ceiling_only:
         print(json.dumps({"ceiling": ceiling_leg()}), flush=True)
+        return
+    if args.mrt_only:
+        print(json.dumps({"mrt": mrt_leg()}), flush=True)
         return
     import torch
 

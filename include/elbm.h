@@ -90,8 +90,9 @@ enum { ELBM_STORE_F32 = 0, ELBM_STORE_F16 = 1, ELBM_STORE_BF16 = 2 };
  *  mode_dir[3]  the velocity direction d whose amplitude
  *               < (d.u) exp(-i k.x) > the diagnostics report (Sec. 3.1).
  *  collision    ELBM_COLLISION_BGK (Sec. 2.1, eq. LBGK) or ELBM_COLLISION_MRT
- *               (D2Q9 only; the multi-relaxation-time extension that Sec. 4
- *               names): the deviatoric non-equilibrium stress relaxes at
+ *               (the multi-relaxation-time extension that Sec. 4 names; D3Q27
+ *               lattices with it take the register-pull kernel, never the
+ *               LDS-staged one): the deviatoric non-equilibrium stress relaxes at
  *               omega, its trace at omega_bulk, the non-equilibrium part
  *               above second order at omega_ghost (the stress parts mapped
  *               back by the linear Grad map of the product-form lattice),

@@ -40,6 +40,7 @@ struct elbm_lattice {
   int64_t step = 0;
   int64_t ntiles = 0;
   bool wall = false, force = false, staged = false;
+  int kind = kKindD2;  // step kernel family (StepKind)
   LatticeDesc desc{};
   LatticeConst64 c64{};
   DiagArgs dargs{};
@@ -79,24 +80,22 @@ int32_t hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, #call);    \
   } while (0)
 
-constexpr int kClasses = 48;  // D (2) x storage (3) x wall (2) x force (2) x staged (2)
+constexpr int kClasses = kKinds * 12;  // kernel kind (4) x storage (3) x wall (2) x force (2)
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-int class_of(int D, int storage, bool wall, bool force, bool staged) {
-  return ((((D == 3) * 3 + storage) * 2 + (wall ? 1 : 0)) * 2 + (force ? 1 : 0)) * 2 + (staged ? 1 : 0);
+int class_of(int kind, int storage, bool wall, bool force) {
+  return ((kind * 3 + storage) * 2 + (wall ? 1 : 0)) * 2 + (force ? 1 : 0);
 }
 static_assert(kClasses == kStaticClasses, "one static table per kernel class");
 
 // The kernel class of index c (inverse of class_of).
 struct ClassKey {
-  int D, storage;
-  bool wall, force, staged;
+  int kind, storage;
+  bool wall, force;
 };
-ClassKey class_key(int c) {
-  return ClassKey{c >= kClasses / 2 ? 3 : 2, (c / 8) % 3, (c / 4) % 2 == 1, (c / 2) % 2 == 1, c % 2 == 1};
-}
+ClassKey class_key(int c) { return ClassKey{c / 12, (c / 4) % 3, (c / 2) % 2 == 1, c % 2 == 1}; }
 
 // Persistent grid of a batched launch: a power of two >= the tiles (capped),
 // so that one captured graph serves every mix of the same size class.
@@ -106,14 +105,15 @@ int batch_grid(int64_t tiles) {
   return int(g);
 }
 
-// Whether a lattice takes the LDS-staged step kernel: D3Q27 with 16-bit
+// Whether a lattice takes the LDS-staged step kernel: D3Q27 LBGK with 16-bit
 // storage, full tiles (n_x % 64 == 0, n_y % kRowsStaged == 0), x and z
 // periodic, y periodic or bounce-back. ELBM_STAGED=0 forces the register-pull
 // kernel (for measurements).
 bool use_staged(const elbm_params& p) {
   if (const char* s = std::getenv("ELBM_STAGED"))
     if (s[0] == '0') return false;
-  return p.lattice == 27 && p.storage != ELBM_STORE_F32 && p.bc[0] == ELBM_BC_PERIODIC &&
+  return p.lattice == 27 && p.collision == ELBM_COLLISION_BGK && p.storage != ELBM_STORE_F32 &&
+         p.bc[0] == ELBM_BC_PERIODIC &&
          p.bc[2] == ELBM_BC_PERIODIC && p.n[0] % 64 == 0 && p.n[1] % kRowsStaged == 0;
 }
 
@@ -198,7 +198,6 @@ int32_t check(const elbm_params* p) {
   if (p->collision != ELBM_COLLISION_BGK && p->collision != ELBM_COLLISION_MRT)
     return fail(ELBM_EINVAL, "collision must be ELBM_COLLISION_BGK or ELBM_COLLISION_MRT");
   if (p->collision == ELBM_COLLISION_MRT) {
-    if (p->lattice != 9) return fail(ELBM_EUNSUPPORTED, "the MRT collision is implemented for D2Q9 lattices only");
     if (!(p->omega_bulk > 0.0 && p->omega_bulk < 2.0) || !(p->omega_ghost > 0.0 && p->omega_ghost < 2.0))
       return fail(ELBM_EINVAL, "omega_bulk and omega_ghost must lie in (0, 2)");
   }
@@ -330,7 +329,7 @@ void fill_desc(elbm_lattice* h) {
   int cus = 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
     cus = 256;
-  const int bpc = step_blocks_per_cu(D, p.storage, h->wall, h->force, h->staged);
+  const int bpc = step_blocks_per_cu(h->kind, p.storage, h->wall, h->force);
   d.chunk = choose_chunk(D, int64_t(d.tiles[0]) * d.tiles[1], d.n[2], int64_t(cus) * bpc);
   d.tiles[2] = (d.n[2] + d.chunk - 1) / d.chunk;
   d.ntiles = int64_t(d.tiles[0]) * d.tiles[1] * d.tiles[2];
@@ -520,6 +519,8 @@ int32_t elbm_create(const elbm_params* p, void* dev_buf, size_t bytes, void* hip
   for (int a = 0; a < h->D; ++a) h->wall = h->wall || p->bc[a] == ELBM_BC_BOUNCEBACK;
   h->force = p->force[0] != 0.0 || p->force[1] != 0.0 || (h->D == 3 && p->force[2] != 0.0);
   h->staged = use_staged(*p);
+  h->kind = h->D == 2 ? kKindD2
+                      : (h->staged ? kKindD3Staged : (p->collision == ELBM_COLLISION_MRT ? kKindD3Mrt : kKindD3));
   hipError_t e = hipGetDevice(&h->device);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&h->event, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -602,12 +603,12 @@ int32_t elbm_step(elbm_handle h, int64_t nsteps) {
     if (sample) {
       // the sample step: the step kernel also forms the record's moments
       // (its tiles spread over at most kDiagBlocks blocks, one partial each)
-      HIPCHK(launch_step_diag(h->D, h->p.storage, h->wall, h->force, h->staged, h->hdr_dev, h->desc_dev, h->step,
-                              grid_diag, h->dargs, h->stream));
+      HIPCHK(launch_step_diag(h->kind, h->p.storage, h->wall, h->force, h->hdr_dev, h->desc_dev, h->step, grid_diag,
+                              h->dargs, h->stream));
       HIPCHK(launch_diag_tail(h->c64, h->ustage, h->partials, grid_diag, h->history, h->hist_count,
                               int32_t(h->p.diag_capacity), h->last, h->step + 1, h->stream));
     } else {
-      HIPCHK(launch_step(h->D, h->p.storage, h->wall, h->force, h->staged, h->hdr_dev, h->desc_dev, h->step, grid,
+      HIPCHK(launch_step(h->kind, h->p.storage, h->wall, h->force, h->hdr_dev, h->desc_dev, h->step, grid,
                          h->stream));
     }
     ++h->step;
@@ -621,11 +622,11 @@ int32_t elbm_kernel(elbm_handle h, elbm_kernel_info* out) {
   if (!h || !out) return fail(ELBM_EINVAL, "NULL argument");
   elbm_kernel_info k{};
   k.kernel = h->staged ? ELBM_KERNEL_STAGED : ELBM_KERNEL_REGISTER;
-  k.block_threads = step_block_threads(h->D, h->staged);
+  k.block_threads = step_block_threads(h->kind);
   k.tile[0] = h->D == 3 ? (h->staged ? 64 : kTileX3) : 64 * kStrips2;
   k.tile[1] = h->D == 3 ? (h->staged ? kRowsStaged : kRows3) : 1;
   k.tile[2] = h->desc.chunk;
-  k.blocks_per_cu = step_blocks_per_cu(h->D, h->p.storage, h->wall, h->force, h->staged);
+  k.blocks_per_cu = step_blocks_per_cu(h->kind, h->p.storage, h->wall, h->force);
   k.tiles = h->ntiles;
   *out = k;
   return ELBM_OK;
@@ -831,7 +832,7 @@ int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps
   for (int32_t k = 0; k < count; ++k) {
     if (steps[k] == 0) continue;
     const elbm_lattice* h = hs[k];
-    members[class_of(h->D, h->p.storage, h->wall, h->force, h->staged)].push_back(k);
+    members[class_of(h->kind, h->p.storage, h->wall, h->force)].push_back(k);
   }
   uint64_t mask = 0;
   std::vector<int> grids;
@@ -884,7 +885,7 @@ int32_t elbm_batch_run(elbm_batch b, const elbm_handle* hs, const int64_t* steps
         const ClassKey ck = class_key(c);
         const auto* hdr = reinterpret_cast<const TableHeader*>(b->dev_tables[c]);
         const auto* tab = reinterpret_cast<const LatticeDesc*>(b->dev_tables[c] + hbytes);
-        HIPCHK(launch_step(ck.D, ck.storage, ck.wall, ck.force, ck.staged, hdr, tab, sub, grids[gi++], st));
+        HIPCHK(launch_step(ck.kind, ck.storage, ck.wall, ck.force, hdr, tab, sub, grids[gi++], st));
       }
     }
     return ELBM_OK;
@@ -978,7 +979,7 @@ int32_t elbm_batch_run_static(const elbm_handle* hs, const int64_t* steps, int32
   for (int32_t k = 0; k < count; ++k)
     if (steps[k] > 0) {
       const elbm_lattice* h = hs[k];
-      ++ncls[class_of(h->D, h->p.storage, h->wall, h->force, h->staged)];
+      ++ncls[class_of(h->kind, h->p.storage, h->wall, h->force)];
     }
   int32_t used = 0;
   for (int c = 0; c < kClasses; ++c) {
@@ -989,7 +990,7 @@ int32_t elbm_batch_run_static(const elbm_handle* hs, const int64_t* steps, int32
   for (int32_t k = 0; k < count; ++k) {
     if (steps[k] == 0) continue;
     const elbm_lattice* h = hs[k];
-    const int c = class_of(h->D, h->p.storage, h->wall, h->force, h->staged);
+    const int c = class_of(h->kind, h->p.storage, h->wall, h->force);
     order[first[c] + ncls[c]++] = k;
   }
   for (int c = 0; c < kClasses; ++c) {
@@ -1018,7 +1019,7 @@ int32_t elbm_batch_run_static(const elbm_handle* hs, const int64_t* steps, int32
     for (int c = 0; c < kClasses; ++c) {
       if (ncls[c] == 0) continue;
       const ClassKey ck = class_key(c);
-      HIPCHK(launch_step(ck.D, ck.storage, ck.wall, ck.force, ck.staged, dhdr + c, dtab + first[c], sub,
+      HIPCHK(launch_step(ck.kind, ck.storage, ck.wall, ck.force, dhdr + c, dtab + first[c], sub,
                          batch_grid(tiles[c]), st));
     }
   // the lattices' streams wait for the run

@@ -189,18 +189,25 @@ struct FaceArgs {
 hipError_t launch_faces(const FaceArgs& a, hipStream_t st);
 
 // ---- launchers (defined in the .hip translation units) ----
-// staged: the LDS-staged D3Q27 kernel for 16-bit storage (periodic, full tiles).
-hipError_t launch_step(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
+// Step kernel families: the D2Q9 register-pull kernel (LBGK, or the
+// multi-relaxation-time collision as a runtime branch), the D3Q27
+// register-pull kernel, the LDS-staged D3Q27 kernel for 16-bit storage
+// (periodic x and z, full tiles), and the D3Q27 register-pull kernel with the
+// multi-relaxation-time collision (a variant of its own: the LBGK kernel's
+// registers are not shared with it).
+enum StepKind : int { kKindD2 = 0, kKindD3 = 1, kKindD3Staged = 2, kKindD3Mrt = 3 };
+constexpr int kKinds = 4;
+hipError_t launch_step(int kind, int storage, bool wall, bool force, const TableHeader* hdr,
                        const LatticeDesc* table, int64_t substep, int grid, hipStream_t st);
 // The same step with the diagnostics of its post-collision state folded in
 // (one lattice per table; grid at most kDiagBlocks blocks, one partial record
 // per block).
-hipError_t launch_step_diag(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
+hipError_t launch_step_diag(int kind, int storage, bool wall, bool force, const TableHeader* hdr,
                             const LatticeDesc* table, int64_t substep, int grid, const DiagArgs& da,
                             hipStream_t st);
-int step_block_threads(int D, bool staged);
+int step_block_threads(int kind);
 // Resident step blocks per compute unit for a kernel class (occupancy query).
-int step_blocks_per_cu(int D, int storage, bool wall, bool force, bool staged);
+int step_blocks_per_cu(int kind, int storage, bool wall, bool force);
 
 hipError_t launch_init(const LatticeConst64& c, const double* stage, int64_t cell0, int64_t count,
                        void* dst, hipStream_t st);

@@ -385,17 +385,19 @@ __device__ __forceinline__ void load_const(const LatticeDesc* __restrict__ Ld, u
 //   o = e + (1 - w)(h - e) with e = scale (f* - w) and h - e exact while the
 //   node is near equilibrium, instead of (1 - w) h + w e, whose two terms
 //   nearly cancel when w is close to 2 (one more operation per population).
-template <int D, bool FORCE, bool ACC, class HV, class EMIT>
+template <int D, bool FORCE, bool ACC, bool MRT3, class HV, class EMIT>
 __device__ __forceinline__ void collide(const TileConst& k, float drho, const float (&dj)[3], const float (&Gd)[3],
                                         HV hval, EMIT emit) {
   constexpr int Q = D == 3 ? 27 : 9;
   const float rho = 1.f + drho;
   const float ir = recip(rho);
   float du[3], dP[3], d[3][3], p[3][3];
-  // D2Q9 multi-relaxation-time collision: the isotropic part of the
-  // anomaly difference takes the bulk rate's factor (internal axes 0, 2)
-  const bool mrt = D == 2 && k.mrt;
-  const float giso = mrt ? 0.5f * (Gd[0] + Gd[2]) : 0.f;
+  // Multi-relaxation-time collision (a runtime branch for D2Q9, the MRT3
+  // kernel variant for D3Q27): the isotropic part of the anomaly difference
+  // (its mean over the axes; D2Q9 uses internal axes 0, 2) takes the bulk
+  // rate's factor
+  const bool mrt = MRT3 || (D == 2 && k.mrt);
+  const float giso = !mrt ? 0.f : (D == 3 ? (Gd[0] + Gd[1] + Gd[2]) * (1.f / 3.f) : 0.5f * (Gd[0] + Gd[2]));
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (D == 2 && a == 1) {
@@ -444,7 +446,7 @@ __device__ __forceinline__ void collide(const TileConst& k, float drho, const fl
   // (c_x, c_y) partial products are applied once per node:
   // m (drho X + dX) p_z + W_x W_y (m d_z) for D3Q27,
   // m (drho W~_x + d_x) p_y + W_x (m d_y) for D2Q9.
-  const float mfold = ACC ? k.scale : k.oms;
+  const float mfold = (ACC || MRT3) ? k.scale : k.oms;
   const float drs = mfold * drho;
   float ds[3][3];
 #pragma unroll
@@ -477,6 +479,72 @@ __device__ __forceinline__ void collide(const TileConst& k, float drho, const fl
       ex[c] = sr * e[0][c];
       qz[c] = pe[2][c] + e[2][c];
     }
+  }
+  if constexpr (D == 3 && MRT3) {
+    // Multi-relaxation-time relaxation in storage scale (as the D2Q9 branch
+    // below, over three axes): fe_i = scale (f*_i - w_i) = A p_z + W_x W_y ds_z
+    // with m = scale, n_i = h_i - fe_i, and
+    //   o_i = fe_i + (1 - og) n_i + (og - o) G_i(Pi_dev) + (og - ob) G_i(Pi_iso),
+    // G_i(Pi) = sum_a dPsi_a/dP Pi_aa prod_{b != a} p_b
+    //         + sum_{a<b} c_a c_b Pi_ab / (4 lam_a lam_b) p_d   (d the third axis).
+    // The second moments of n are those of h less those of fe, which the
+    // product form gives in closed form: sum c_a^2 f* = rho (p_a+ + p_a-),
+    // sum c_a c_b f* = rho (p_a+ - p_a-)(p_b+ - p_b-), and the same of w with
+    // the reference triplets W (written in deviations: rho = 1 + drho,
+    // p = W + d), so no fe_i is formed before the emitting pass.
+    float s2[3] = {0.f, 0.f, 0.f}, s11[3] = {0.f, 0.f, 0.f};  // sum c_a^2 h; sum c_x c_y h, c_x c_z h, c_y c_z h
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const int c0 = cq<3>(i, 0), c1 = cq<3>(i, 1), c2 = cq<3>(i, 2);
+      const float hv = hval(i);
+      if (c0 != 0) s2[0] += hv;
+      if (c1 != 0) s2[1] += hv;
+      if (c2 != 0) s2[2] += hv;
+      if (c0 * c1 > 0) s11[0] += hv;
+      if (c0 * c1 < 0) s11[0] -= hv;
+      if (c0 * c2 > 0) s11[1] += hv;
+      if (c0 * c2 < 0) s11[1] -= hv;
+      if (c1 * c2 > 0) s11[2] += hv;
+      if (c1 * c2 < 0) s11[2] -= hv;
+    }
+    const float sc = k.scale;
+    float pd[3], U[3], dl[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float e2 = sc * (drho * (k.W[a][0] + k.W[a][2]) + rho * (d[a][0] + d[a][2]));
+      pd[a] = (s2[a] - e2) * (k.lam[a] * k.lam[a]);
+      U[a] = k.W[a][2] - k.W[a][0];  // u_ref / lam
+      dl[a] = d[a][2] - d[a][0];     // du / lam
+    }
+    auto e11 = [&](int a, int b) {
+      return sc * (drho * U[a] * U[b] + rho * (U[a] * dl[b] + dl[a] * U[b] + dl[a] * dl[b]));
+    };
+    const float qxy = 0.25f * (s11[0] - e11(0, 1)), qxz = 0.25f * (s11[1] - e11(0, 2));
+    const float qyz = 0.25f * (s11[2] - e11(1, 2));
+    const float tr = (pd[0] + pd[1] + pd[2]) * (1.f / 3.f);
+    const float dv0 = pd[0] - tr, dv1 = pd[1] - tr, dv2 = pd[2] - tr;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const int c0 = cq<3>(i, 0) + 1, c1 = cq<3>(i, 1) + 1, c2 = cq<3>(i, 2) + 1;
+      const float fe = A[c0][c1] * p[2][c2] + k.WW[c0][c1] * ds[2][c2];
+      const float nq = hval(i) - fe;
+      const float gx = c0 == 1 ? -k.inv_lam2[0] : 0.5f * k.inv_lam2[0];
+      const float gy = c1 == 1 ? -k.inv_lam2[1] : 0.5f * k.inv_lam2[1];
+      const float gz = c2 == 1 ? -k.inv_lam2[2] : 0.5f * k.inv_lam2[2];
+      const float px = p[0][c0], py = p[1][c1], pz = p[2][c2];
+      const float tx = gx * py * pz, ty = px * gy * pz, tz = px * py * gz;
+      const float gdev = tx * dv0 + ty * dv1 + tz * dv2 + float((c0 - 1) * (c1 - 1)) * qxy * pz +
+                         float((c0 - 1) * (c2 - 1)) * qxz * py + float((c1 - 1) * (c2 - 1)) * qyz * px;
+      const float gis = (tx + ty + tz) * tr;
+      float o = fe + k.om1g * nq + k.cdev * gdev + k.ciso * gis;
+      if (FORCE) {
+        const float Y = sx[c0] * pe[1][c1];
+        const float dY = ex[c0] * (pe[1][c1] + e[1][c1]) + sx[c0] * e[1][c1];
+        o += dY * qz[c2] + Y * e[2][c2];
+      }
+      emit(i, o);
+    }
+    return;
   }
   if constexpr (D == 2) {
     if (mrt) {
@@ -702,7 +770,7 @@ __device__ __forceinline__ void diag_block_store(const double* __restrict__ wsum
   if (j == kDF) partials[blockIdx.x * kRec + R_STEP] = 0.0;
 }
 
-template <int D, int S, bool WALL, bool FORCE, bool DIAG>
+template <int D, int S, bool WALL, bool FORCE, bool DIAG, bool MRT3>
 __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, int64_t tl, int parity,
                                           float* __restrict__ sq, const DiagArgs& da, double* __restrict__ wslot) {
   using G = Geo<D, S>;
@@ -962,7 +1030,7 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
       Gd[2] = (qnext - qprev) * hz;
 
       const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
-      collide<D, FORCE, S == 0>(k, drho, dj, Gd, [&](int i) { return h.get(i); },
+      collide<D, FORCE, S == 0, MRT3>(k, drho, dj, Gd, [&](int i) { return h.get(i); },
                         [&](int i, float o) { Store<S>::store(rd, no.own, i * sb, o); });
       if constexpr (DIAG)
         diag_node<D>(da, [&](int i) { return h.get(i); }, gx, gy, z,
@@ -1326,7 +1394,7 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
       Gd[1] = (qyp - qym) * k.hil[1];
       Gd[2] = (qn[2] - qprev) * hz;
       const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
-      collide<3, FORCE, S == 0>(k, drho, dj, Gd, [&](int i) { return Store<S>::to_float(cur.get(i)); },
+      collide<3, FORCE, S == 0, false>(k, drho, dj, Gd, [&](int i) { return Store<S>::to_float(cur.get(i)); },
                         [&](int i, float o) { Store<S>::store(rd, own, i * sb, o); });
     }
     QX(b ^ 1, sx_own) = qn[0];
@@ -1385,7 +1453,7 @@ __global__ void __launch_bounds__(lds::NT)
   if constexpr (DIAG) diag_block_store<lds::NT / 64>(wsum, da.partials);
 }
 
-template <int D, int S, bool WALL, bool FORCE, bool DIAG>
+template <int D, int S, bool WALL, bool FORCE, bool DIAG, bool MRT3>
 __global__ void __launch_bounds__(Threads<D>::value)
     step_kernel(const TableHeader* __restrict__ hdr, const LatticeDesc* __restrict__ table, int64_t substep,
                 DiagArgs da) {
@@ -1407,34 +1475,34 @@ __global__ void __launch_bounds__(Threads<D>::value)
     const LatticeDesc* d = table + L;
     if (substep < d->nsteps) {
       const int parity = (d->parity0 + int(substep & 1)) & 1;
-      step_tile<D, S, WALL, FORCE, DIAG>(d, t - d->tile_base, parity, sq, da, wslot);
+      step_tile<D, S, WALL, FORCE, DIAG, MRT3>(d, t - d->tile_base, parity, sq, da, wslot);
     }
     __syncthreads();
   }
   if constexpr (DIAG) diag_block_store<Threads<D>::value / 64>(wsum, da.partials);
 }
 
-template <int D, int S, bool WALL, bool FORCE>
+template <int D, int S, bool WALL, bool FORCE, bool MRT3>
 hipError_t launch_one(const TableHeader* hdr, const LatticeDesc* table, int64_t substep, int grid,
                       const DiagArgs* da, hipStream_t st) {
   if (da)
-    hipLaunchKernelGGL((step_kernel<D, S, WALL, FORCE, true>), dim3(grid), dim3(Geo<D, S>::NT), 0, st, hdr, table,
-                       substep, *da);
+    hipLaunchKernelGGL((step_kernel<D, S, WALL, FORCE, true, MRT3>), dim3(grid), dim3(Geo<D, S>::NT), 0, st, hdr,
+                       table, substep, *da);
   else
-    hipLaunchKernelGGL((step_kernel<D, S, WALL, FORCE, false>), dim3(grid), dim3(Geo<D, S>::NT), 0, st, hdr,
+    hipLaunchKernelGGL((step_kernel<D, S, WALL, FORCE, false, MRT3>), dim3(grid), dim3(Geo<D, S>::NT), 0, st, hdr,
                        table, substep, DiagArgs{});
   return hipGetLastError();
 }
 
-template <int D, int S>
+template <int D, int S, bool MRT3>
 hipError_t launch_ds(bool wall, bool force, const TableHeader* hdr, const LatticeDesc* table, int64_t s,
                      int grid, const DiagArgs* da, hipStream_t st) {
   if (wall) {
-    return force ? launch_one<D, S, true, true>(hdr, table, s, grid, da, st)
-                 : launch_one<D, S, true, false>(hdr, table, s, grid, da, st);
+    return force ? launch_one<D, S, true, true, MRT3>(hdr, table, s, grid, da, st)
+                 : launch_one<D, S, true, false, MRT3>(hdr, table, s, grid, da, st);
   }
-  return force ? launch_one<D, S, false, true>(hdr, table, s, grid, da, st)
-               : launch_one<D, S, false, false>(hdr, table, s, grid, da, st);
+  return force ? launch_one<D, S, false, true, MRT3>(hdr, table, s, grid, da, st)
+               : launch_one<D, S, false, false, MRT3>(hdr, table, s, grid, da, st);
 }
 
 template <int S, bool FORCE, bool WALLY>
@@ -1460,13 +1528,15 @@ hipError_t launch_lds_s(bool wall, bool force, const TableHeader* hdr, const Lat
 
 }  // namespace
 
-int step_block_threads(int D, bool staged) { return staged ? lds::NT : (D == 3 ? Geo<3, 0>::NT : Geo<2, 0>::NT); }
+int step_block_threads(int kind) {
+  return kind == kKindD3Staged ? lds::NT : (kind == kKindD2 ? Geo<2, 0>::NT : Geo<3, 0>::NT);
+}
 
-template <int D, int S, bool WALL, bool FORCE>
+template <int D, int S, bool WALL, bool FORCE, bool MRT3>
 int occupancy_one() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<D, S, WALL, FORCE, false>, Geo<D, S>::NT, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<D, S, WALL, FORCE, false, MRT3>, Geo<D, S>::NT,
+                                                   0) != hipSuccess)
     return 1;
   return n > 0 ? n : 1;
 }
@@ -1486,66 +1556,70 @@ int occupancy_lds_s(bool wall, bool force) {
   return force ? occupancy_lds<S, true, false>() : occupancy_lds<S, false, false>();
 }
 
-template <int D, int S>
+template <int D, int S, bool MRT3>
 int occupancy_ds(bool wall, bool force) {
-  if (wall) return force ? occupancy_one<D, S, true, true>() : occupancy_one<D, S, true, false>();
-  return force ? occupancy_one<D, S, false, true>() : occupancy_one<D, S, false, false>();
+  if (wall) return force ? occupancy_one<D, S, true, true, MRT3>() : occupancy_one<D, S, true, false, MRT3>();
+  return force ? occupancy_one<D, S, false, true, MRT3>() : occupancy_one<D, S, false, false, MRT3>();
 }
 
-int step_blocks_per_cu(int D, int storage, bool wall, bool force, bool staged) {
-  if (staged && D == 3 && storage != 0) return storage == 1 ? occupancy_lds_s<1>(wall, force)
-                                                             : occupancy_lds_s<2>(wall, force);
-  if (D == 3) {
-    switch (storage) {
-      case 0: return occupancy_ds<3, 0>(wall, force);
-      case 1: return occupancy_ds<3, 1>(wall, force);
-      default: return occupancy_ds<3, 2>(wall, force);
-    }
-  }
+template <int D, bool MRT3>
+int occupancy_s(int storage, bool wall, bool force) {
   switch (storage) {
-    case 0: return occupancy_ds<2, 0>(wall, force);
-    case 1: return occupancy_ds<2, 1>(wall, force);
-    default: return occupancy_ds<2, 2>(wall, force);
+    case 0: return occupancy_ds<D, 0, MRT3>(wall, force);
+    case 1: return occupancy_ds<D, 1, MRT3>(wall, force);
+    default: return occupancy_ds<D, 2, MRT3>(wall, force);
+  }
+}
+
+int step_blocks_per_cu(int kind, int storage, bool wall, bool force) {
+  switch (kind) {
+    case kKindD3Staged:
+      return storage == 1 ? occupancy_lds_s<1>(wall, force) : occupancy_lds_s<2>(wall, force);
+    case kKindD3: return occupancy_s<3, false>(storage, wall, force);
+    case kKindD3Mrt: return occupancy_s<3, true>(storage, wall, force);
+    default: return occupancy_s<2, false>(storage, wall, force);
   }
 }
 
 namespace {
-hipError_t launch_any(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
+template <int D, bool MRT3>
+hipError_t launch_s(int storage, bool wall, bool force, const TableHeader* hdr, const LatticeDesc* table,
+                    int64_t substep, int grid, const DiagArgs* da, hipStream_t st) {
+  switch (storage) {
+    case 0: return launch_ds<D, 0, MRT3>(wall, force, hdr, table, substep, grid, da, st);
+    case 1: return launch_ds<D, 1, MRT3>(wall, force, hdr, table, substep, grid, da, st);
+    case 2: return launch_ds<D, 2, MRT3>(wall, force, hdr, table, substep, grid, da, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_any(int kind, int storage, bool wall, bool force, const TableHeader* hdr,
                       const LatticeDesc* table, int64_t substep, int grid, const DiagArgs* da, hipStream_t st) {
   if (grid <= 0 || (grid & 7)) return hipErrorInvalidConfiguration;
-  if (staged) {
-    // (wall: bounce-back on y only; the host admits no other walls here)
-    if (D != 3 || (storage != 1 && storage != 2)) return hipErrorInvalidValue;
-    return storage == 1 ? launch_lds_s<1>(wall, force, hdr, table, substep, grid, da, st)
-                        : launch_lds_s<2>(wall, force, hdr, table, substep, grid, da, st);
-  }
-  if (D == 3) {
-    switch (storage) {
-      case 0: return launch_ds<3, 0>(wall, force, hdr, table, substep, grid, da, st);
-      case 1: return launch_ds<3, 1>(wall, force, hdr, table, substep, grid, da, st);
-      case 2: return launch_ds<3, 2>(wall, force, hdr, table, substep, grid, da, st);
-    }
-  } else if (D == 2) {
-    switch (storage) {
-      case 0: return launch_ds<2, 0>(wall, force, hdr, table, substep, grid, da, st);
-      case 1: return launch_ds<2, 1>(wall, force, hdr, table, substep, grid, da, st);
-      case 2: return launch_ds<2, 2>(wall, force, hdr, table, substep, grid, da, st);
-    }
+  switch (kind) {
+    case kKindD3Staged:
+      // (wall: bounce-back on y only; the host admits no other walls here)
+      if (storage != 1 && storage != 2) return hipErrorInvalidValue;
+      return storage == 1 ? launch_lds_s<1>(wall, force, hdr, table, substep, grid, da, st)
+                          : launch_lds_s<2>(wall, force, hdr, table, substep, grid, da, st);
+    case kKindD3: return launch_s<3, false>(storage, wall, force, hdr, table, substep, grid, da, st);
+    case kKindD3Mrt: return launch_s<3, true>(storage, wall, force, hdr, table, substep, grid, da, st);
+    case kKindD2: return launch_s<2, false>(storage, wall, force, hdr, table, substep, grid, da, st);
   }
   return hipErrorInvalidValue;
 }
 }  // namespace
 
-hipError_t launch_step(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
+hipError_t launch_step(int kind, int storage, bool wall, bool force, const TableHeader* hdr,
                        const LatticeDesc* table, int64_t substep, int grid, hipStream_t st) {
-  return launch_any(D, storage, wall, force, staged, hdr, table, substep, grid, nullptr, st);
+  return launch_any(kind, storage, wall, force, hdr, table, substep, grid, nullptr, st);
 }
 
-hipError_t launch_step_diag(int D, int storage, bool wall, bool force, bool staged, const TableHeader* hdr,
+hipError_t launch_step_diag(int kind, int storage, bool wall, bool force, const TableHeader* hdr,
                             const LatticeDesc* table, int64_t substep, int grid, const DiagArgs& da,
                             hipStream_t st) {
   if (grid > kDiagBlocks || !da.ustage || !da.partials) return hipErrorInvalidValue;
-  return launch_any(D, storage, wall, force, staged, hdr, table, substep, grid, &da, st);
+  return launch_any(kind, storage, wall, force, hdr, table, substep, grid, &da, st);
 }
 
 }  // namespace elbm

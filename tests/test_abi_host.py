@@ -58,12 +58,11 @@ def test_walls_with_advection_reference_are_unsupported(D):
 
 
 def test_mrt_collision_validation():
-    """The multi-relaxation-time collision: D2Q9 only, rates in (0, 2), and a
-    collision code the library knows."""
+    """The multi-relaxation-time collision: D2Q9 and D3Q27, rates in (0, 2),
+    and a collision code the library knows."""
     assert E.validate(E.make_params((32, 16), T=0.5, omega=1.6, omega_bulk=1.1, omega_ghost=1.3)) == E.OK
-    p3 = E.make_params((8, 8, 8), T=0.5, omega=1.6, omega_bulk=1.1)
-    assert E.validate(p3) == E.EUNSUPPORTED
-    assert "D2Q9" in E._lib.elbm_last_error().decode()
+    assert E.validate(E.make_params((8, 8, 8), T=0.5, omega=1.6, omega_bulk=1.1)) == E.OK
+    assert E.validate(E.make_params((8, 8, 8), T=0.5, omega=1.6, omega_ghost=2.0)) == E.EINVAL
     for ob, og in ((0.0, 1.0), (1.0, 2.0), (-0.5, 1.0), (1.0, float("nan"))):
         assert E.validate(E.make_params((32, 16), T=0.5, omega=1.6, omega_bulk=ob, omega_ghost=og)) == E.EINVAL
         assert "omega_bulk" in E._lib.elbm_last_error().decode()
