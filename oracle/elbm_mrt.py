@@ -32,7 +32,8 @@ way: its isotropic part (the mean over the axes of d_a Q~_a) takes
 (2 - omega_bulk)/(2 omega_bulk), its deviatoric part (2 - omega)/(2 omega).
 (With the BGK factor on both parts, the sound waves of a stretched lattice
 decay at a rate that depends on the stretching; with the split they decay by
-(nu + nu_bulk) k^2 / 2 on every lattice, tests/test_oracle_mrt.py.)
+(nu + nu_bulk) k^2 / 2 on every D2Q9 lattice and by (2 nu + nu_bulk) k^2 / 3
+on D3Q27, nu_bulk = (1/omega_bulk - 1/2) T, tests/test_oracle_mrt.py.)
 """
 
 from __future__ import annotations
