@@ -204,6 +204,53 @@ def test_d3q27_shear_wave_viscosity(ob, og):
     lat.close()
 
 
+@pytest.mark.parametrize("mode", ["batch", "batch_graph", "static"])
+def test_mrt_lattices_in_batched_launches(mode):
+    """MRT lattices batched with LBGK lattices of the same shapes (their own
+    kernel classes: the D3Q27 MRT variant, the D2Q9 kernel's runtime branch)
+    advance bitwise as alone, through the batch object with and without
+    HIP-graph replay and through the allocation-free entry point."""
+    E = lib()
+    specs = [
+        ((48, 24, 24), (2.0, 1.0, 1.0), (False, True, False), (1e-5, 0.0, 0.0), "f32", (1.2, 1.0)),
+        ((48, 24, 24), (2.0, 1.0, 1.0), (False, True, False), (1e-5, 0.0, 0.0), "f32", None),
+        ((64, 32, 16), (1.0, 1.0, 1.0), (False, False, False), None, "f16", (0.9, 1.6)),
+        ((64, 32, 16), (1.0, 1.0, 1.0), (False, False, False), None, "f16", None),
+        ((96, 40), (2.0, 1.0), (False, True), (5e-5, 0.0), "f32", (1.3, 1.1)),
+        ((96, 40), (2.0, 1.0), (False, True), (5e-5, 0.0), "f32", None),
+        ((70, 37, 21), (1.4, 1.0, 2.0), (False, False, False), None, "bf16", (1.1, 1.3)),
+    ]
+    steps = [6, 9, 4, 7, 11, 3, 5]
+
+    def make():
+        out = []
+        for k, (n, lam, walls, force, st, rates) in enumerate(specs):
+            p = O.Params(n=n, lam=lam, T=0.5, omega=1.7, walls=walls, force=force)
+            kw = dict(omega_bulk=rates[0], omega_ghost=rates[1]) if rates else {}
+            lat = E.Lattice(E.make_params(n, lam=lam, T=0.5, omega=1.7, walls=walls, force=force, storage=st,
+                                          **kw))
+            lat.set_populations(random_state(p, seed=40 + k))
+            out.append(lat)
+        return out
+
+    alone = make()
+    for lat, k in zip(alone, steps):
+        lat.step(k)
+    ref = [lat.populations() for lat in alone]
+    batched = make()
+    if mode == "static":
+        E.batch_run_static(batched, steps)
+    else:
+        b = E.Batch(len(batched))
+        b.run(batched, steps, use_graph=mode == "batch_graph")
+        b.close()
+    for lat, k, r in zip(batched, steps, ref):
+        assert lat.step_count == k
+        assert np.array_equal(lat.populations(), r)
+    for lat in alone + batched:
+        lat.close()
+
+
 def test_mrt_is_rejected_where_not_implemented():
     E = lib()
     lat = E.Lattice(E.make_params((8, 8), T=1 / 3, omega=1.2, omega_bulk=1.1))
