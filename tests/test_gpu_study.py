@@ -197,3 +197,49 @@ def test_channel_study_driver_runs(tmp_path):
     assert np.isfinite(up).all() and up.size == 96
     assert 0 < up[0] < up[-1] < 30
     assert np.isfinite(res["re_tau_measured"])
+
+
+# ---- the multi-relaxation-time collision on a shear layer LBGK cannot run ----
+#
+# The double shear layer at Re = 3e4 (u0 = 0.1) on 256^2 cubic nodes, T = 1/2
+# (omega = 1.9932): the step linearised about the layer's stream has modes
+# growing ~2% per step with LBGK and none with the MRT collision at
+# omega_bulk = 1, omega_ghost = 1.5 (tests/test_oracle_mrt.py). Measured on
+# one MI355X: LBGK diverges before t* = 0.4 (at 128^2-1024^2 before
+# t* = 0.2-0.5); MRT runs to t* = 1 and ends within 0.2% (kinetic energy) and
+# 1.7% (enstrophy) of LBGK at the paper's T = 1/3, where LBGK is stable.
+
+DSL_N, DSL_RE = 256, 3.0e4
+
+
+def _dsl_run(T, rates):
+    E = lib()
+    n = (DSL_N, DSL_N)
+    omega = 1.0 / (U * DSL_N / DSL_RE / T + 0.5)
+    kw = dict(omega_bulk=rates[0], omega_ghost=rates[1]) if rates else {}
+    fld = I.double_shear_layer(n, U=U)
+    lat = E.Lattice(E.make_params(n, T=T, omega=omega, **kw))
+    lat.init(fld.rho, fld.u)
+    steps = int(round(DSL_N / U))
+    out = None
+    for k in range(10):
+        lat.step(steps // 10)
+        d = lat.diag(check=False)
+        if d["nan_count"] > 0 or not math.isfinite(d["ke"]):
+            out = {"diverged_at": (k + 1) / 10}
+            break
+    else:
+        out = {"ke": d["ke"], "enstrophy": d["enstrophy"]}
+    lat.close()
+    return out
+
+
+def test_mrt_runs_the_shear_layer_that_lbgk_cannot():
+    lbgk_hot = _dsl_run(0.5, None)
+    mrt_hot = _dsl_run(0.5, (1.0, 1.5))
+    lbgk_cold = _dsl_run(1.0 / 3.0, None)
+    MEASURED.append(dict(test="dsl_mrt_256", lbgk_t05=lbgk_hot, mrt_t05=mrt_hot, lbgk_t033=lbgk_cold))
+    assert "diverged_at" in lbgk_hot
+    assert "ke" in mrt_hot and "ke" in lbgk_cold
+    assert abs(mrt_hot["ke"] / lbgk_cold["ke"] - 1.0) < 5e-3
+    assert abs(mrt_hot["enstrophy"] / lbgk_cold["enstrophy"] - 1.0) < 5e-2

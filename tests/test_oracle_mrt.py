@@ -199,3 +199,30 @@ def test_d3q27_long_waves(ob, og):
     nub = (1.0 / ob - 0.5) * 0.5
     assert -np.angle(rat[-1]) / (cs * k) == pytest.approx(1.0, abs=1e-4)
     assert -math.log(abs(rat[-1])) / ((2.0 * nu + nub) * k * k / 3.0) == pytest.approx(1.0, abs=2e-3)
+
+
+@pytest.mark.parametrize("T,rates,unstable", [
+    (0.5, None, True), (0.5, (1.0, 1.0), False), (0.5, (1.0, 1.5), False),
+    (1 / 3, None, False), (1 / 3, (1.0, 1.0), True), (1 / 3, (1.0, 1.5), False),
+])
+def test_linear_stability_of_the_shear_layer_stream(T, rates, unstable):
+    """The double shear layer's stream (u = 0.1 along x) at the viscosity of
+    Re = 3e4 on 256 nodes (omega = 1.99), cubic D2Q9, linearised about the
+    uniform state (wave vectors on a 17 x 33 grid of the Brillouin zone):
+    at T = 1/2 LBGK has modes growing by about 2% per step and the MRT
+    collision with omega_bulk = 1 (omega_ghost = 1 or 1.5) none; at T = 1/3
+    LBGK is stable and omega_ghost = 1 is not (0.9% per step), omega_ghost =
+    1.5 is. The GPU runs of the shear layer follow this (tests/test_gpu_study.py)."""
+    lam, omega, U = (1.0, 1.0), 1.99, (0.1, 0.0)
+    worst = 0.0
+    for kx in np.linspace(0.0, math.pi, 17):
+        for ky in np.linspace(-math.pi, math.pi, 33):
+            if rates is None:
+                M = step_matrix((kx, ky), U, T, omega, lam)
+            else:
+                M = mrt_step_matrix((kx, ky), U, T, omega, lam, *rates)
+            worst = max(worst, float(np.abs(np.linalg.eigvals(M)).max()))
+    if unstable:
+        assert worst > 1.005
+    else:
+        assert worst < 1.0 + 1e-9
