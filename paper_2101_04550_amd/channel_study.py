@@ -30,6 +30,7 @@ half a node below the first row), with u_tau from the force balance and from
 the mean wall gradient. Output: one JSON document.
 
 Usage: python -m paper_2101_04550_amd.channel_study --lattice stretched --tstar 30 --out result.json
+       (--omega-bulk B --omega-ghost G: the multi-relaxation-time collision)
 """
 from __future__ import annotations
 
@@ -99,7 +100,9 @@ def wall_units(prof, c, y):
         turbulent=bool(np.mean(vrms / ut_force) > 0.2))
 
 
-def run(lattice, tstar, stats_from, sample, storage, out, seed_offset=3):
+def run(lattice, tstar, stats_from, sample, storage, out, seed_offset=3, rates=None):
+    """rates: (omega_bulk, omega_ghost) of the multi-relaxation-time collision,
+    or None for LBGK."""
     import torch  # noqa: F401
 
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -111,8 +114,9 @@ def run(lattice, tstar, stats_from, sample, storage, out, seed_offset=3):
     n, lam, H = c["n"], c["lam"], c["H"]
     steps_total = int(round(tstar * H / c["u_tau"]))
     fld = I.channel_field(n, lam, u0=c["u0"], seed_offset=seed_offset)
+    kw = dict(omega_bulk=rates[0], omega_ghost=rates[1]) if rates else {}
     lat = E.Lattice(E.make_params(n, lam=lam, T=c["T"], omega=c["omega"], walls=(False, True, False),
-                                  force=(c["g"], 0.0, 0.0), storage=storage))
+                                  force=(c["g"], 0.0, 0.0), storage=storage, **kw))
     lat.init(fld.rho, fld.u)
     y = (np.arange(n[1]) + 0.5) * lam[1]              # distance from the lower wall
     series, acc, nacc = [], None, 0
@@ -141,7 +145,8 @@ def run(lattice, tstar, stats_from, sample, storage, out, seed_offset=3):
         print(f"# {lattice} step {done}/{steps_total} t*={ts:.2f} bulk={series[-1]['bulk']:.5f} "
               f"v'rms(centre)={series[-1]['v_rms_centre']:.2e} ({time.time() - t0:.0f} s)", flush=True)
     lat.close()
-    res = dict(lattice=lattice, storage=storage, n=n, lam=lam, constants=c, steps=steps_total, tstar=tstar,
+    res = dict(lattice=lattice, storage=storage, collision="mrt" if rates else "lbgk",
+               rates=list(rates) if rates else None, n=n, lam=lam, constants=c, steps=steps_total, tstar=tstar,
                stats_from=stats_from, samples_averaged=nacc, series=series)
     if nacc:
         res.update(wall_units(acc / nacc, c, y))
@@ -160,8 +165,16 @@ def main(argv=None):
     ap.add_argument("--sample", type=int, default=5000)
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--out", default="channel_study.json")
+    ap.add_argument("--omega-bulk", type=float, default=None,
+                    help="with --omega-ghost: the multi-relaxation-time collision (default LBGK)")
+    ap.add_argument("--omega-ghost", type=float, default=None)
     a = ap.parse_args(argv)
-    run(a.lattice, a.tstar, a.stats_from, a.sample, a.storage, a.out)
+    rates = None
+    if a.omega_bulk is not None or a.omega_ghost is not None:
+        c = setup(a.lattice)
+        rates = (a.omega_bulk if a.omega_bulk is not None else c["omega"],
+                 a.omega_ghost if a.omega_ghost is not None else c["omega"])
+    run(a.lattice, a.tstar, a.stats_from, a.sample, a.storage, a.out, rates=rates)
 
 
 if __name__ == "__main__":

@@ -1,6 +1,8 @@
 """GPU studies of stretched lattices against regular ones: the periodic double
-shear layer of Sec. 3.3, and (at the end of this file) the laminar flat plate
-of Sec. 3.4 with Grad's-approximation walls.
+shear layer of Sec. 3.3, and (further down) the laminar flat plate of Sec. 3.4
+with Grad's-approximation walls, the temperature independence of decaying
+turbulence, the channel driver, and (at the end) two flows whose parameters
+LBGK cannot run and the multi-relaxation-time collision can.
 
 Double shear layer: on the cubic lattice and on the lattice stretched to
 lambda = (2, 1) with half the x nodes.
@@ -243,3 +245,45 @@ def test_mrt_runs_the_shear_layer_that_lbgk_cannot():
     assert "ke" in mrt_hot and "ke" in lbgk_cold
     assert abs(mrt_hot["ke"] / lbgk_cold["ke"] - 1.0) < 5e-3
     assert abs(mrt_hot["enstrophy"] / lbgk_cold["enstrophy"] - 1.0) < 5e-2
+
+
+def _bench_channel_run(rates, steps=6000, every=2000):
+    """The benchmark channel (384 x 192 x 192, lambda = (2, 1, 1), T = 1/2,
+    Re_tau = 180 force) from the seeded laminar-plus-noise start: the step at
+    which the velocity first turns non-finite (sampled every `every` steps),
+    or None, and the final bulk velocity."""
+    from paper_2101_04550_amd import channel_study as CS
+
+    E = lib()
+    c = CS.setup("bench")
+    fld = I.channel_field(c["n"], c["lam"], u0=c["u0"], seed_offset=3)
+    kw = dict(omega_bulk=rates[0], omega_ghost=rates[1]) if rates else {}
+    lat = E.Lattice(E.make_params(c["n"], lam=c["lam"], T=c["T"], omega=c["omega"], walls=(False, True, False),
+                                  force=(c["g"], 0.0, 0.0), **kw))
+    lat.init(fld.rho, fld.u)
+    bad, bulk = None, None
+    for done in range(every, steps + 1, every):
+        lat.step(every)
+        _, u = lat.fields()
+        if not np.isfinite(u).all():
+            bad = done
+            break
+        bulk = float(u[0].mean())
+    lat.close()
+    return bad, bulk
+
+
+def test_benchmark_channel_runs_with_mrt_not_lbgk():
+    """The benchmark channel's parameters (omega = 1.9768 on lambda = (2, 1,
+    1) at T = 1/2) let LBGK diverge within a few thousand steps; the MRT
+    collision with omega_bulk = omega_ghost = 1.5 runs them (6000 steps
+    here; to t* = 30 with channel_study.py, turbulent, Re_tau 176.6 from the
+    wall gradient) with the bulk velocity near the seed's. Measured: LBGK
+    non-finite by step 3000."""
+    bad_lbgk, _ = _bench_channel_run(None)
+    bad_mrt, bulk = _bench_channel_run((1.5, 1.5))
+    MEASURED.append(dict(test="bench_channel_mrt", lbgk_nonfinite_at=bad_lbgk, mrt_nonfinite_at=bad_mrt,
+                         mrt_bulk=bulk))
+    assert bad_lbgk is not None
+    assert bad_mrt is None
+    assert 0.06 < bulk < 0.09
