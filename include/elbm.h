@@ -331,6 +331,10 @@ int32_t elbm_batch_run_static(const elbm_handle* hs, const int64_t* steps, int32
  *                      velocity interpolated through the wall, the density
  *                      of the node's mass and normal-momentum balance and
  *                      the Navier-Stokes stress of the interpolated velocity
+ *                      (with the MRT collision: its trace part at
+ *                      omega_bulk; with omega_bulk != omega the wall then
+ *                      misses the bulk's second-order normal stresses and
+ *                      exchanges mass with the flow at that order)
  *  ELBM_FACE_INLET     prescribed velocity inlet_velocity[f] at the halfway
  *                      plane (bounce-back from a surface moving at it)
  *  ELBM_FACE_OUTLET    prescribed density outlet_density[f], with the inward
@@ -365,8 +369,7 @@ typedef struct elbm_faces_params {
 typedef struct elbm_faces_s* elbm_faces_handle;
 
 /* Device bytes of the face tables of `lattice` (node lists, ghost list,
- * per-node moments). The lattice must be D2Q9 with FP32 storage, the LBGK
- * collision, u_adv = 0
+ * per-node moments). The lattice must be D2Q9 with FP32 storage, u_adv = 0
  * and both axes periodic (bc), and it must carry the ghost ring: its
  * extents are the fluid extents plus 2 along every axis whose faces are not
  * PERIODIC (fluid extents >= 3 there). ELBM_EINVAL / ELBM_EUNSUPPORTED with

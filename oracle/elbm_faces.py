@@ -31,7 +31,10 @@ the missing ones are set, per the kind of the face the node is on:
     S_0 + 2 S_out (S_0: known populations with c_n = 0, S_out: those moving
     out through the face, s = +1 on a low face, -1 on a high face);
   - Pi_t = rho_t (T I + u_t u_t) + Pi_neq, Pi_neq = -(rho_t T / omega)
-    (grad u_t + grad u_t^T): the normal derivative s (u_f - u_w) /
+    (grad u_t + grad u_t^T) (with the multi-relaxation-time collision of
+    ``elbm_mrt``: the deviatoric part of grad u_t + grad u_t^T over omega,
+    its trace part over omega_bulk, the rates the bulk relaxes those parts
+    at): the normal derivative s (u_f - u_w) /
     (3 lambda_n / 2), the tangential one a central difference of u_f along
     the face over 3 (as u_t = (2 u_w + u_f)/3 with u_w constant);
   - f^G_i = rho_t Psi_{c_ix}(u_t,x, P_xx) Psi_{c_iy}(u_t,y, P_yy)
@@ -78,6 +81,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import elbm_oracle as O
+from . import elbm_mrt as OM
 
 PERIODIC, SYMMETRY, WALL, INLET, OUTLET = 0, 1, 2, 3, 4
 FACES = ("x-", "x+", "y-", "y+")
@@ -171,8 +175,10 @@ def _outlet(f, fpost, p, fc, F, x, y, xf, M):
         f[i, y, x] = f_out[i] + f[i, xf[1], xf[0]] - f_nb[i]
 
 
-def stream_open(fpost, p: O.Params, fc: Faces):
-    """Pull streaming with the open-boundary rules (module docstring)."""
+def stream_open(fpost, p: O.Params, fc: Faces, omega_bulk=None):
+    """Pull streaming with the open-boundary rules (module docstring);
+    omega_bulk: the trace rate of the multi-relaxation-time collision (None:
+    LBGK)."""
     c = p.c
     nx, ny = p.n
     lam = p.lam
@@ -240,7 +246,11 @@ def stream_open(fpost, p: O.Params, fc: Faces):
             _, u_m = _node_state(fpost, p, *wrap(*tm))
             grad[t_ax] = (u_p - u_m) / (2.0 * lam[t_ax]) / 3.0
             S = grad + grad.T
-            Pi_neq = -(rho_t * p.T / p.omega) * S
+            if omega_bulk is None:
+                Pi_neq = -(rho_t * p.T / p.omega) * S
+            else:
+                iso = 0.5 * np.trace(S) * np.eye(2)
+                Pi_neq = -(rho_t * p.T) * ((S - iso) / p.omega + iso / omega_bulk)
             fg = grad_populations(rho_t, ut, Pi_neq, p.T, lam, c)
             for i in M:
                 f[i, y, x] = fg[i]
@@ -308,14 +318,25 @@ def collide_open(f, p: O.Params, fc: Faces):
     return fnew
 
 
-def step_open(fpost, p: O.Params, fc: Faces):
-    """One time step with open boundaries: pull with the face rules, then collide."""
+def collide_open_mrt(f, p: O.Params, fc: Faces, omega_bulk: float, omega_ghost: float):
+    """``elbm_mrt.collide`` with the face ghosts in the anomaly difference."""
+    rho, j = O.moments(f, p.c, p.lam)
+    P = OM.pressure(rho, j, p, omega_bulk, diff=lambda q, a: central_difference_open(q, a, p, fc))
+    return OM.relax(f, p, rho, j / rho, P, omega_bulk, omega_ghost)
+
+
+def step_open(fpost, p: O.Params, fc: Faces, rates=None):
+    """One time step with open boundaries: pull with the face rules, then
+    collide (LBGK, or the multi-relaxation-time collision at rates =
+    (omega_bulk, omega_ghost))."""
     if any(p.walls):
         raise ValueError("open faces replace the bounce-back walls: Params.walls must be all False")
-    return collide_open(stream_open(fpost, p, fc), p, fc)
+    if rates is None:
+        return collide_open(stream_open(fpost, p, fc), p, fc)
+    return collide_open_mrt(stream_open(fpost, p, fc, rates[0]), p, fc, *rates)
 
 
-def run_open(fpost, p: O.Params, fc: Faces, nsteps: int):
+def run_open(fpost, p: O.Params, fc: Faces, nsteps: int, rates=None):
     for _ in range(int(nsteps)):
-        fpost = step_open(fpost, p, fc)
+        fpost = step_open(fpost, p, fc, rates)
     return fpost

@@ -74,14 +74,19 @@ def grad_map(Pi, u, P, lam, c):
     return out
 
 
-def pressure(rho, j, p: O.Params, omega_bulk: float):
+def pressure(rho, j, p: O.Params, omega_bulk: float, diff=None):
     """Diagonal pressure of the collision target with the correction split
-    into its isotropic and deviatoric parts (module docstring)."""
+    into its isotropic and deviatoric parts (module docstring). ``diff(q, a)``
+    is the central difference of the anomaly along axis a (default: the
+    lattice's own, periodic or next to bounce-back walls)."""
     u = j / rho
     P = O.equilibrium_pressure(u, p.T)
     if p.extended:
         Qt = O.anomaly(rho, j, p.T, p.lam)
-        G = [O.central_difference(Qt[a], a, p.lam[a], p.walls[a], p.D) for a in range(p.D)]
+        if diff is None:
+            G = [O.central_difference(Qt[a], a, p.lam[a], p.walls[a], p.D) for a in range(p.D)]
+        else:
+            G = [diff(Qt[a], a) for a in range(p.D)]
         iso = sum(G) / p.D
         cd = (2.0 - p.omega) / (2.0 * rho * p.omega)
         cb = (2.0 - omega_bulk) / (2.0 * rho * omega_bulk)
@@ -90,13 +95,11 @@ def pressure(rho, j, p: O.Params, omega_bulk: float):
     return P
 
 
-def collide(f, p: O.Params, omega_bulk: float, omega_ghost: float):
-    """Multi-relaxation-time collision (module docstring), plus the body force."""
+def relax(f, p: O.Params, rho, u, P, omega_bulk: float, omega_ghost: float):
+    """The relaxation of the module docstring towards the product form at
+    (rho, u, P), plus the body force."""
     c = p.c
     D = p.D
-    rho, j = O.moments(f, c, p.lam)
-    u = j / rho
-    P = pressure(rho, j, p, omega_bulk)
     fstar = O.product_form(rho, u, P, p.lam, c)
     fneq = f - fstar
     v = [p.lam[a] * c[:, a].astype(np.float64) for a in range(D)]
@@ -111,6 +114,12 @@ def collide(f, p: O.Params, omega_bulk: float, omega_ghost: float):
         g = np.array(p.force).reshape((D,) + (1,) * D)
         fnew = fnew + O.equilibrium(rho, u + g, p.T, p.lam, c) - O.equilibrium(rho, u, p.T, p.lam, c)
     return fnew
+
+
+def collide(f, p: O.Params, omega_bulk: float, omega_ghost: float):
+    """Multi-relaxation-time collision (module docstring), plus the body force."""
+    rho, j = O.moments(f, p.c, p.lam)
+    return relax(f, p, rho, j / rho, pressure(rho, j, p, omega_bulk), omega_bulk, omega_ghost)
 
 
 def step(fpost, p: O.Params, omega_bulk: float, omega_ghost: float):

@@ -1057,8 +1057,6 @@ int32_t plan_faces(const elbm_lattice* h, const elbm_faces_params* fp, FacePlan&
   if (fp->abi_version != ELBM_ABI_VERSION) return fail(ELBM_EINVAL, "faces abi_version mismatch");
   if (h->D != 2) return fail(ELBM_EUNSUPPORTED, "open faces are implemented for D2Q9 lattices only");
   if (h->p.storage != ELBM_STORE_F32) return fail(ELBM_EUNSUPPORTED, "open faces need FP32 storage");
-  if (h->p.collision != ELBM_COLLISION_BGK)
-    return fail(ELBM_EUNSUPPORTED, "open faces need the LBGK collision (their Grad rule relaxes at one rate)");
   if (h->p.u_adv[0] != 0.0 || h->p.u_adv[1] != 0.0)
     return fail(ELBM_EUNSUPPORTED, "open faces need u_adv == 0 (rest reference)");
   if (h->p.bc[0] != ELBM_BC_PERIODIC || h->p.bc[1] != ELBM_BC_PERIODIC)
@@ -1206,6 +1204,7 @@ int32_t elbm_faces_create(elbm_handle h, const elbm_faces_params* fp, void* dev_
   }
   A.T = h->p.T;
   A.omega = h->p.omega;
+  A.omega_bulk = h->p.collision == ELBM_COLLISION_MRT ? h->p.omega_bulk : h->p.omega;
   for (int i = 0; i < 9; ++i) A.w[i] = h->c64.W[0][i % 3] * h->c64.W[1][i / 3];
   for (int F = 0; F < 4; ++F) {
     A.wall_u[F] = fp->wall_velocity[F];

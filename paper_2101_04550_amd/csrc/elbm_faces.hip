@@ -26,7 +26,9 @@
 //            u_f at 3 lambda_n/2), the density of the mass and
 //            normal-momentum balance rho_t (1 - s u_t,n/lambda_n) =
 //            S_0 + 2 S_out, and the stress rho_t (T + u_t u_t)
-//            - (rho_t T/omega)(grad u_t + grad u_t^T);
+//            - (rho_t T/omega)(grad u_t + grad u_t^T) (under the
+//            multi-relaxation-time collision the trace part of
+//            grad u_t + grad u_t^T over omega_bulk instead);
 //  INLET     f_i = f'_{-i}(x) + f^eq_i(rho_x, u_in) - f^eq_{-i}(rho_x, u_in):
 //            bounce-back from a surface moving at u_in at the halfway plane,
 //            with the equilibrium of Sec. 2.3 (eq. 27eq) at the node's own
@@ -128,8 +130,12 @@ __device__ void boundary_rule(const View& v, const FaceNode& nd, double (&fm)[9]
     v.state(t_ax == 0 ? xf + 1 : xf, t_ax == 1 ? yf + 1 : yf, rp, up);
     v.state(t_ax == 0 ? xf - 1 : xf, t_ax == 1 ? yf - 1 : yf, rm, um);
     for (int b = 0; b < 2; ++b) grad[t_ax][b] = (up[b] - um[b]) / (2.0 * A.lam[t_ax]) / 3.0;
-    const double k = -(rt * A.T / A.omega);
-    const double pxx = k * 2.0 * grad[0][0], pyy = k * 2.0 * grad[1][1], pxy = k * (grad[0][1] + grad[1][0]);
+    // Pi_neq = -rho_t T (S_dev / omega + S_iso / omega_bulk), S = grad u + grad u^T,
+    // S_iso = m I with m = (S_xx + S_yy) / 2 (omega_bulk = omega under LBGK)
+    const double m = grad[0][0] + grad[1][1];
+    const double kd = -(rt * A.T / A.omega), kb = -(rt * A.T / A.omega_bulk);
+    const double pxx = kd * (2.0 * grad[0][0] - m) + kb * m, pyy = kd * (2.0 * grad[1][1] - m) + kb * m;
+    const double pxy = kd * (grad[0][1] + grad[1][0]);
     const double Px = A.T + ut[0] * ut[0] + pxx / rt, Py = A.T + ut[1] * ut[1] + pyy / rt;
     for (int i = 0; i < 9; ++i) {
       if (!miss[i]) continue;

@@ -174,6 +174,7 @@ struct FaceArgs {
   int32_t o[2];           // 1 on an open axis (ghost ring), 0 on a periodic one
   int32_t n[2];           // fluid extents
   double lam[2], T, omega, g[2];
+  double omega_bulk;      // trace rate of the MRT collision (omega under LBGK)
   double w[9];            // reference weights of the deviations
   double wall_u[4];       // tangential wall velocity per face
   double inlet_u[4][2];   // inlet velocity per face

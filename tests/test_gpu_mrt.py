@@ -249,12 +249,3 @@ def test_mrt_lattices_in_batched_launches(mode):
         assert np.array_equal(lat.populations(), r)
     for lat in alone + batched:
         lat.close()
-
-
-def test_mrt_is_rejected_where_not_implemented():
-    E = lib()
-    lat = E.Lattice(E.make_params((8, 8), T=1 / 3, omega=1.2, omega_bulk=1.1))
-    with pytest.raises(E.ElbmError) as ei:
-        E.Faces(lat, ["periodic", "periodic", "wall", "wall"])
-    assert ei.value.status == E.EUNSUPPORTED
-    lat.close()
