@@ -4,7 +4,9 @@ product-form equilibrium.
 TEST INFRASTRUCTURE ONLY, like ``elbm_oracle``.
 
 The paper's conclusion (Sec. 4) names multi-relaxation-time collisions as a
-direct extension of the model without giving one. The reading taken here
+direct extension of the model without giving one, so parity against the
+paper is unpinned; the pins in tests/test_oracle_mrt.py are the limits and
+properties any such collision must have. The reading taken here
 relaxes three parts of the non-equilibrium f^neq = f - f* (f* the extended
 product-form equilibrium of Sec. 2.3-2.4, as in ``elbm_oracle.collide``)
 at three rates:

@@ -249,3 +249,30 @@ def test_mrt_lattices_in_batched_launches(mode):
         assert np.array_equal(lat.populations(), r)
     for lat in alone + batched:
         lat.close()
+
+
+def test_mrt_checkpoint_resumes_bitwise_and_checks_the_rates():
+    """elbm_save / elbm_load of an MRT lattice: a resumed run is bitwise the
+    uninterrupted one; a checkpoint does not load into a lattice with other
+    rates or the LBGK collision."""
+    E = lib()
+    p = O.Params(n=(48, 24, 24), lam=(2.0, 1.0, 1.0), T=0.5, omega=1.9, walls=(False, True, False),
+                 force=(1e-5, 0.0, 0.0))
+    kw = dict(lam=p.lam, T=p.T, omega=p.omega, walls=p.walls, force=p.force)
+    lat = E.Lattice(E.make_params(p.n, omega_bulk=1.2, omega_ghost=1.0, **kw))
+    lat.set_populations(random_state(p, seed=8))
+    lat.step(5)
+    ck = lat.save()
+    lat.step(7)
+    want = lat.populations()
+    other = E.Lattice(E.make_params(p.n, omega_bulk=1.2, omega_ghost=1.0, **kw))
+    other.load(ck)
+    other.step(7)
+    assert np.array_equal(other.populations(), want)
+    for bad in (E.make_params(p.n, omega_bulk=1.3, omega_ghost=1.0, **kw), E.make_params(p.n, **kw)):
+        L = E.Lattice(bad)
+        with pytest.raises(E.ElbmError):
+            L.load(ck)
+        L.close()
+    lat.close()
+    other.close()
