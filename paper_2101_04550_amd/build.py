@@ -1,5 +1,6 @@
 """Builds libelbm.so (HIP kernels for gfx950 + the C ABI) and the bandwidth
-probe libelbm_probe.so in the package directory.
+probe libelbm_probe.so in the package directory, and the plain C client of
+the ABI (tests/c/abi_run.c) into _build/abi_run.
 
 Usage: python -m paper_2101_04550_amd.build   (or build() from Python)
 
@@ -26,6 +27,10 @@ SOURCES = ["elbm_step.hip", "elbm_aux.hip", "elbm_static.hip", "elbm_faces.hip",
 PROBE_SOURCES = ["elbm_probe.hip"]
 PROBE_LIB = os.path.join(PKG, "libelbm_probe.so")
 ARCH = "gfx950"
+# a C program that runs the step through the ABI alone (tests/test_gpu_c_client.py)
+C_CLIENT = os.path.join(ROOT, "tests", "c", "abi_run.c")
+C_CLIENT_EXE = os.path.join(BUILD, "abi_run")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 
 def hipcc():
@@ -70,14 +75,30 @@ def _link(objs, out, verbose):
     os.replace(tmp, out)
 
 
+def _c_client(verbose):
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        raise RuntimeError("no C compiler for the ABI client")
+    cmd = [cc, "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-I", INCLUDE, "-I", os.path.join(ROCM, "include"),
+           C_CLIENT, "-o", C_CLIENT_EXE, "-L", PKG, "-l:libelbm.so", f"-Wl,-rpath,{PKG}",
+           "-L", os.path.join(ROCM, "lib"), "-lamdhip64", f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"build of the C client failed:\n{r.stdout}\n{r.stderr}")
+
+
 def build(verbose: bool = False) -> str:
-    """Builds libelbm.so and the bandwidth probe libelbm_probe.so."""
+    """Builds libelbm.so, the bandwidth probe libelbm_probe.so and the C
+    client of the ABI."""
     os.makedirs(BUILD, exist_ok=True)
     sources = SOURCES + PROBE_SOURCES
     with cf.ThreadPoolExecutor(max_workers=len(sources)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), sources))
     _link(objs[:len(SOURCES)], LIB, verbose)
     _link(objs[len(SOURCES):], PROBE_LIB, verbose)
+    _c_client(verbose)
     return LIB
 
 
