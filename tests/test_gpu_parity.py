@@ -449,3 +449,38 @@ def test_enstrophy_3d_closed_form_on_gpu(walls):
     MEASURED.append(dict(test="enstrophy_closed_form", case=f"walls={walls}", storage="f32", component="enstrophy",
                          measured=float(e), target=1e-5, bound=1e-5))
     assert e <= 1e-5
+
+
+def test_empty_and_zero_step_requests():
+    """Degenerate requests: zero steps leave a lattice bitwise unchanged (step
+    count 0), negative steps are rejected, an empty batch and a batch whose
+    step counts are all zero are no-ops (also through the allocation-free
+    entry point), and zero face steps change nothing."""
+    E = lib()
+    p = O.Params(n=(32, 16, 8), T=0.5, omega=1.6)
+    lat = E.Lattice(params_for(p))
+    lat.set_populations(random_state(p, seed=31))
+    f0 = lat.populations()
+    lat.step(0)
+    assert lat.step_count == 0
+    assert np.array_equal(lat.populations(), f0)
+    with pytest.raises(E.ElbmError) as ei:
+        lat.step(-1)
+    assert ei.value.status == E.EINVAL
+    b = E.Batch(4)
+    b.run([], [])
+    b.run([lat], [0])
+    E.batch_run_static([], [])
+    E.batch_run_static([lat], [0])
+    assert lat.step_count == 0
+    assert np.array_equal(lat.populations(), f0)
+    b.close()
+    lat.close()
+    lat2 = E.Lattice(E.make_params((8, 10), T=1 / 3, omega=1.2))
+    lat2.set_populations(random_state(O.Params(n=(8, 10), T=1 / 3, omega=1.2), seed=32))
+    faces = E.Faces(lat2, ["periodic", "periodic", "wall", "wall"])
+    g0 = lat2.populations()
+    faces.step(0)
+    assert np.array_equal(lat2.populations(), g0)
+    faces.close()
+    lat2.close()
