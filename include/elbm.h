@@ -225,8 +225,11 @@ int32_t elbm_step(elbm_handle h, int64_t nsteps);
 int64_t elbm_step_count(elbm_handle h);
 
 /* The step kernel and launch shape chosen for this lattice (fixed at
- * elbm_create; the environment variable ELBM_STAGED=0 forces the register
- * kernel). ELBM_EINVAL on NULL arguments. Host only. */
+ * elbm_create). Two environment variables read at elbm_create override the
+ * choice, for measurements: ELBM_STAGED=0 forces the register kernel, and
+ * ELBM_CHUNK=c (an integer >= 1) sets the planes marched per tile (capped at
+ * the lattice's extent along that axis; every value gives the same results).
+ * ELBM_EINVAL on NULL arguments. Host only. */
 int32_t elbm_kernel(elbm_handle h, elbm_kernel_info* out);
 
 /* Macroscopic fields of the current state, FP64, host arrays owned by the
