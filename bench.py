@@ -541,6 +541,7 @@ def main():
     if args.n == N_HIT and not args.hit_only:
         out["d2q9"] = d2q9_leg()
         out["channel"] = channel_leg()
+        out["mrt"] = mrt_leg()
     if args.n == N_HIT and not args.no_ceiling:
         out["ceiling"] = ceiling_leg()
         out["roofline"]["ceiling_gbs"] = out["ceiling"]["best_gbs"]
