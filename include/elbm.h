@@ -375,7 +375,11 @@ typedef struct elbm_faces_s* elbm_faces_handle;
  * per-node moments). The lattice must be D2Q9 with FP32 storage, u_adv = 0
  * and both axes periodic (bc), and it must carry the ghost ring: its
  * extents are the fluid extents plus 2 along every axis whose faces are not
- * PERIODIC (fluid extents >= 3 there). ELBM_EINVAL / ELBM_EUNSUPPORTED with
+ * PERIODIC (fluid extents >= 3 there). A D3Q27 lattice takes the faces of a
+ * channel: PERIODIC x faces, WALL y faces (one kind per face, node_kind
+ * NULL; wall_velocity[2], [3]: the x-velocity of the low and the high wall),
+ * z periodic, FP32 storage, u_adv = 0, all axes periodic in bc and n_y the
+ * fluid rows (>= 3) plus 2 ghost rows. ELBM_EINVAL / ELBM_EUNSUPPORTED with
  * a message otherwise. Host arithmetic only. */
 int32_t elbm_faces_query_bytes(elbm_handle lattice, const elbm_faces_params* fp, size_t* bytes);
 

@@ -22,7 +22,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libelbm.so")
 
-SOURCES = ["elbm_step.hip", "elbm_aux.hip", "elbm_static.hip", "elbm_faces.hip", "elbm_api.cpp"]
+SOURCES = ["elbm_step.hip", "elbm_aux.hip", "elbm_static.hip", "elbm_faces.hip", "elbm_walls3d.hip",
+           "elbm_api.cpp"]
 # bandwidth probe of the step's access pattern (measurement only)
 PROBE_SOURCES = ["elbm_probe.hip"]
 PROBE_LIB = os.path.join(PKG, "libelbm_probe.so")

@@ -1037,7 +1037,9 @@ int32_t elbm_batch_run_static(const elbm_handle* hs, const int64_t* steps, int32
 
 struct elbm_faces_s {
   elbm_lattice* h = nullptr;
-  FaceArgs args{};
+  int D = 2;
+  FaceArgs args{};      // D2Q9 open faces
+  Walls3Args args3{};   // D3Q27 Grad walls on the y faces
 };
 
 namespace {
@@ -1051,6 +1053,28 @@ struct FacePlan {
 };
 
 bool face_odd(int kind) { return kind == ELBM_FACE_SYMMETRY || kind == ELBM_FACE_WALL; }
+
+// D3Q27: Grad walls on both y faces, x and z periodic; the storage carries one
+// ghost row below and one above the fluid. Device bytes: the wall nodes'
+// pulled (rho, j_y).
+int32_t plan_walls3(const elbm_lattice* h, const elbm_faces_params* fp, size_t& bytes) {
+  if (h->p.storage != ELBM_STORE_F32) return fail(ELBM_EUNSUPPORTED, "Grad walls need FP32 storage");
+  if (h->p.u_adv[0] != 0.0 || h->p.u_adv[1] != 0.0 || h->p.u_adv[2] != 0.0)
+    return fail(ELBM_EUNSUPPORTED, "Grad walls need u_adv == 0 (rest reference)");
+  for (int a = 0; a < 3; ++a)
+    if (h->p.bc[a] != ELBM_BC_PERIODIC)
+      return fail(ELBM_EINVAL, "the lattice under Grad walls is periodic (bc); the walls replace its bounce-back");
+  if (fp->kind[0] != ELBM_FACE_PERIODIC || fp->kind[1] != ELBM_FACE_PERIODIC || fp->kind[2] != ELBM_FACE_WALL ||
+      fp->kind[3] != ELBM_FACE_WALL)
+    return fail(ELBM_EUNSUPPORTED, "D3Q27 lattices take Grad walls on both y faces with x (and z) periodic");
+  for (int F = 0; F < 4; ++F)
+    if (fp->node_kind[F]) return fail(ELBM_EUNSUPPORTED, "D3Q27 walls take one kind per face (node_kind NULL)");
+  if (h->p.n[1] < 5) return fail(ELBM_EINVAL, "n_y must be the fluid rows (>= 3) plus 2 ghost rows");
+  if (!std::isfinite(fp->wall_velocity[2]) || !std::isfinite(fp->wall_velocity[3]))
+    return fail(ELBM_EINVAL, "wall velocities must be finite");
+  bytes = align_up(size_t(2) * size_t(h->p.n[0]) * size_t(h->p.n[2]) * 2 * sizeof(double), kAlign);
+  return ELBM_OK;
+}
 
 int32_t plan_faces(const elbm_lattice* h, const elbm_faces_params* fp, FacePlan& P) {
   if (!h || !fp) return fail(ELBM_EINVAL, "NULL argument");
@@ -1161,6 +1185,10 @@ extern "C" {
 
 int32_t elbm_faces_query_bytes(elbm_handle lattice, const elbm_faces_params* fp, size_t* bytes) {
   if (!bytes) return fail(ELBM_EINVAL, "NULL argument");
+  if (lattice && fp && lattice->D == 3) {
+    if (fp->abi_version != ELBM_ABI_VERSION) return fail(ELBM_EINVAL, "faces abi_version mismatch");
+    return plan_walls3(lattice, fp, *bytes);
+  }
   FacePlan P;
   const int32_t s = plan_faces(lattice, fp, P);
   if (s) return s;
@@ -1172,6 +1200,38 @@ int32_t elbm_faces_create(elbm_handle h, const elbm_faces_params* fp, void* dev_
                           elbm_faces_handle* out) {
   if (!out) return fail(ELBM_EINVAL, "out is NULL");
   *out = nullptr;
+  if (h && fp && h->D == 3) {
+    if (fp->abi_version != ELBM_ABI_VERSION) return fail(ELBM_EINVAL, "faces abi_version mismatch");
+    size_t need = 0;
+    int32_t s3 = plan_walls3(h, fp, need);
+    if (s3) return s3;
+    if (!dev_buf) return fail(ELBM_EINVAL, "dev_buf is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) return fail(ELBM_EINVAL, "dev_buf must be 256-byte aligned");
+    if (bytes < need)
+      return fail(ELBM_ENOMEM, "device buffer holds " + std::to_string(bytes) + " bytes, " + std::to_string(need) +
+                                   " needed");
+    auto* f = new (std::nothrow) elbm_faces_s();
+    if (!f) return fail(ELBM_EINVAL, "out of host memory");
+    f->h = h;
+    f->D = 3;
+    Walls3Args& A = f->args3;
+    A.pstride = h->pstride;
+    for (int a = 0; a < 3; ++a) {
+      A.N[a] = int32_t(h->p.n[a]);
+      A.n[a] = int32_t(h->p.n[a]) - (a == 1 ? 2 : 0);
+      A.lam[a] = h->p.lambda[a];
+      A.g[a] = h->p.force[a];
+    }
+    A.T = h->p.T;
+    A.omega = h->p.omega;
+    A.omega_bulk = h->p.collision == ELBM_COLLISION_MRT ? h->p.omega_bulk : h->p.omega;
+    for (int i = 0; i < 27; ++i) A.w[i] = h->c64.W[0][i % 3] * h->c64.W[1][(i / 3) % 3] * h->c64.W[2][i / 9];
+    A.wall_u[0] = fp->wall_velocity[2];
+    A.wall_u[1] = fp->wall_velocity[3];
+    A.mom = static_cast<double*>(dev_buf);
+    *out = f;
+    return ELBM_OK;
+  }
   FacePlan P;
   int32_t s = plan_faces(h, fp, P);
   if (s) return s;
@@ -1229,8 +1289,13 @@ int32_t elbm_faces_step(elbm_faces_handle f, int64_t nsteps) {
   int32_t s = set_dev(h->device);
   if (s) return s;
   for (int64_t k = 0; k < nsteps; ++k) {
-    f->args.h = static_cast<float*>(state_buf(h));
-    HIPCHK(launch_faces(f->args, h->stream));
+    if (f->D == 3) {
+      f->args3.h = static_cast<float*>(state_buf(h));
+      HIPCHK(launch_walls3(f->args3, h->stream));
+    } else {
+      f->args.h = static_cast<float*>(state_buf(h));
+      HIPCHK(launch_faces(f->args, h->stream));
+    }
     s = elbm_step(h, 1);
     if (s) return s;
   }

@@ -189,6 +189,20 @@ struct FaceArgs {
 // one face, then corners, then the ghosts' anomaly populations).
 hipError_t launch_faces(const FaceArgs& a, hipStream_t st);
 
+// Grad's-approximation walls on the y faces of a D3Q27 lattice (x and z
+// periodic): the storage carries one ghost row below and one above the fluid.
+struct Walls3Args {
+  float* h;               // state buffer (FP32 deviations), plane slabs along z
+  int64_t pstride;
+  int32_t N[3];           // storage extents (n_y + 2 rows)
+  int32_t n[3];           // fluid extents
+  double lam[3], T, omega, omega_bulk, g[3];
+  double w[27];           // reference weights of the deviations
+  double wall_u[2];       // x-velocity of the low and the high wall
+  double* mom;            // 2 doubles per wall node (pulled rho, j_y), low face then high face
+};
+hipError_t launch_walls3(const Walls3Args& a, hipStream_t st);
+
 // ---- launchers (defined in the .hip translation units) ----
 // Step kernel families: the D2Q9 register-pull kernel (LBGK, or the
 // multi-relaxation-time collision as a runtime branch), the D3Q27
