@@ -1,7 +1,8 @@
 """Turbulent channel at Re_tau = 180 (Sec. 3.5) run long enough for statistics,
 through the library's C ABI.
 
-Geometry: walls in y (halfway bounce-back, half width H = 96 rows,
+Geometry: walls in y (halfway bounce-back, or with --walls grad Grad's
+approximation as Sec. 3 uses; half width H = 96 rows,
 lambda_y = 1), periodic x and z. Lattices:
   stretched -- Sec. 3.5's: 5.6H x 2H x 2H on 384 x 192 x 192 nodes with
                lambda_x = 1.4, T = 0.55;
@@ -100,9 +101,11 @@ def wall_units(prof, c, y):
         turbulent=bool(np.mean(vrms / ut_force) > 0.2))
 
 
-def run(lattice, tstar, stats_from, sample, storage, out, seed_offset=3, rates=None):
+def run(lattice, tstar, stats_from, sample, storage, out, seed_offset=3, rates=None, walls="bounce-back"):
     """rates: (omega_bulk, omega_ghost) of the multi-relaxation-time collision,
-    or None for LBGK."""
+    or None for LBGK; walls: "bounce-back" (halfway bounce-back of the step
+    kernel) or "grad" (Grad's-approximation walls, elbm_faces_* on a lattice
+    with one ghost row below and one above the fluid)."""
     import torch  # noqa: F401
 
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -115,18 +118,34 @@ def run(lattice, tstar, stats_from, sample, storage, out, seed_offset=3, rates=N
     steps_total = int(round(tstar * H / c["u_tau"]))
     fld = I.channel_field(n, lam, u0=c["u0"], seed_offset=seed_offset)
     kw = dict(omega_bulk=rates[0], omega_ghost=rates[1]) if rates else {}
-    lat = E.Lattice(E.make_params(n, lam=lam, T=c["T"], omega=c["omega"], walls=(False, True, False),
-                                  force=(c["g"], 0.0, 0.0), storage=storage, **kw))
-    lat.init(fld.rho, fld.u)
+    grad = walls == "grad"
+    if grad:
+        ns = (n[0], n[1] + 2, n[2])
+        rho0 = np.ones((ns[2], ns[1], ns[0]))
+        u0 = np.zeros((3, ns[2], ns[1], ns[0]))
+        rho0[:, 1:-1, :] = fld.rho
+        u0[:, :, 1:-1, :] = fld.u
+        lat = E.Lattice(E.make_params(ns, lam=lam, T=c["T"], omega=c["omega"], force=(c["g"], 0.0, 0.0),
+                                      storage=storage, **kw))
+        lat.init(rho0, u0)
+        faces = E.Faces(lat, ["periodic", "periodic", "wall", "wall"])
+        advance = faces.step
+    else:
+        lat = E.Lattice(E.make_params(n, lam=lam, T=c["T"], omega=c["omega"], walls=(False, True, False),
+                                      force=(c["g"], 0.0, 0.0), storage=storage, **kw))
+        lat.init(fld.rho, fld.u)
+        advance = lat.step
     y = (np.arange(n[1]) + 0.5) * lam[1]              # distance from the lower wall
     series, acc, nacc = [], None, 0
     t0 = time.time()
     done = 0
     while done < steps_total:
         k = min(sample, steps_total - done)
-        lat.step(k)
+        advance(k)
         done += k
         rho, u = lat.fields()
+        if grad:
+            rho, u = rho[:, 1:-1, :], u[:, :, 1:-1, :]
         if not np.isfinite(u).all():
             raise RuntimeError(f"non-finite velocity at step {done}")
         mean, rms = planar_stats(u)
@@ -144,8 +163,10 @@ def run(lattice, tstar, stats_from, sample, storage, out, seed_offset=3, rates=N
             nacc += 1
         print(f"# {lattice} step {done}/{steps_total} t*={ts:.2f} bulk={series[-1]['bulk']:.5f} "
               f"v'rms(centre)={series[-1]['v_rms_centre']:.2e} ({time.time() - t0:.0f} s)", flush=True)
+    if grad:
+        faces.close()
     lat.close()
-    res = dict(lattice=lattice, storage=storage, collision="mrt" if rates else "lbgk",
+    res = dict(lattice=lattice, storage=storage, walls=walls, collision="mrt" if rates else "lbgk",
                rates=list(rates) if rates else None, n=n, lam=lam, constants=c, steps=steps_total, tstar=tstar,
                stats_from=stats_from, samples_averaged=nacc, series=series)
     if nacc:
@@ -168,13 +189,15 @@ def main(argv=None):
     ap.add_argument("--omega-bulk", type=float, default=None,
                     help="with --omega-ghost: the multi-relaxation-time collision (default LBGK)")
     ap.add_argument("--omega-ghost", type=float, default=None)
+    ap.add_argument("--walls", choices=("bounce-back", "grad"), default="bounce-back",
+                    help="halfway bounce-back (the step kernel's) or Grad's approximation (Sec. 3)")
     a = ap.parse_args(argv)
     rates = None
     if a.omega_bulk is not None or a.omega_ghost is not None:
         c = setup(a.lattice)
         rates = (a.omega_bulk if a.omega_bulk is not None else c["omega"],
                  a.omega_ghost if a.omega_ghost is not None else c["omega"])
-    run(a.lattice, a.tstar, a.stats_from, a.sample, a.storage, a.out, rates=rates)
+    run(a.lattice, a.tstar, a.stats_from, a.sample, a.storage, a.out, rates=rates, walls=a.walls)
 
 
 if __name__ == "__main__":

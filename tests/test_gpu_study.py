@@ -205,16 +205,18 @@ def test_hit_with_the_mrt_collision(hit_temperatures):
     assert dr < 0.02, dr
 
 
-def test_channel_study_driver_runs(tmp_path):
+@pytest.mark.parametrize("walls", ["bounce-back", "grad"])
+def test_channel_study_driver_runs(tmp_path, walls):
     """The Sec. 3.5 statistics driver end to end on its stretched lattice
-    (384 x 192 x 192, lambda_x = 1.4, T = 0.55) for a few hundred steps: the
-    run, the planar statistics and the wall-unit reduction produce finite
-    profiles; the near-wall u+ of the seeded laminar-plus-noise start lies
-    below the log law's centre-line value."""
+    (384 x 192 x 192, lambda_x = 1.4, T = 0.55) for a few hundred steps, with
+    halfway bounce-back or Grad walls: the run, the planar statistics and the
+    wall-unit reduction produce finite profiles; the near-wall u+ of the
+    seeded laminar-plus-noise start lies below the log law's centre-line
+    value."""
     from paper_2101_04550_amd import channel_study as CS
 
     res = CS.run("stretched", tstar=0.02, stats_from=0.0, sample=100, storage="f32",
-                 out=str(tmp_path / "channel.json"))
+                 out=str(tmp_path / "channel.json"), walls=walls)
     assert res["samples_averaged"] >= 2
     up = np.array(res["u_plus"])
     assert np.isfinite(up).all() and up.size == 96
