@@ -153,9 +153,10 @@ enum { ELBM_KERNEL_REGISTER = 0, ELBM_KERNEL_STAGED = 1 };
 typedef struct elbm_kernel_info {
   int32_t kernel;         /* ELBM_KERNEL_REGISTER: each node pulls its Q values
                              with one load apiece; ELBM_KERNEL_STAGED: a block
-                             stages the rows its tile pulls from in LDS (D3Q27,
-                             16-bit storage, n_x % 64 == 0, n_y % 16 == 0, x and
-                             z periodic, y periodic or bounce-back) */
+                             stages the rows its tile pulls from in LDS (D3Q27
+                             LBGK, 16-bit storage, n_x % 64 == 0, x and z
+                             periodic, y bounce-back with n_y % 16 == 0 or
+                             periodic with n_y > 8) */
   int32_t block_threads;  /* threads per workgroup */
   int32_t tile[3];        /* tile extent along the internal axes: x, y (1 for
                              D2Q9), and the planes marched per tile */

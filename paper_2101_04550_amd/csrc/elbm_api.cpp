@@ -106,15 +106,17 @@ int batch_grid(int64_t tiles) {
 }
 
 // Whether a lattice takes the LDS-staged step kernel: D3Q27 LBGK with 16-bit
-// storage, full tiles (n_x % 64 == 0, n_y % kRowsStaged == 0), x and z
-// periodic, y periodic or bounce-back. ELBM_STAGED=0 forces the register-pull
-// kernel (for measurements).
+// storage, n_x % 64 == 0, x and z periodic, y bounce-back with
+// n_y % kRowsStaged == 0 or periodic with n_y > kRowsStaged / 2 (the last tile
+// row may overhang the axis; every row it stages lies within one period).
+// ELBM_STAGED=0 forces the register-pull kernel (for measurements).
 bool use_staged(const elbm_params& p) {
   if (const char* s = std::getenv("ELBM_STAGED"))
     if (s[0] == '0') return false;
   return p.lattice == 27 && p.collision == ELBM_COLLISION_BGK && p.storage != ELBM_STORE_F32 &&
          p.bc[0] == ELBM_BC_PERIODIC &&
-         p.bc[2] == ELBM_BC_PERIODIC && p.n[0] % 64 == 0 && p.n[1] % kRowsStaged == 0;
+         p.bc[2] == ELBM_BC_PERIODIC && p.n[0] % 64 == 0 &&
+         (p.bc[1] == ELBM_BC_PERIODIC ? p.n[1] > kRowsStaged / 2 : p.n[1] % kRowsStaged == 0);
 }
 
 bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }

@@ -67,10 +67,12 @@ namespace {
 // Population arrays are accessed through buffer resources: a uniform base
 // address (direction and plane, in scalar registers) plus a 32-bit per-lane
 // byte offset that stays fixed along the march. Bounds checking is left open
-// (num_records = 2^32 - 1); every offset is in range by construction.
+// (num_records = 2^32 - 1); every offset is in range by construction. A
+// resource of zero records is the one exception: the hardware's range check
+// drops every store through it (the staged kernel's rows beyond n_y).
 using Rsrc = __amdgpu_buffer_rsrc_t;
-__device__ __forceinline__ Rsrc rsrc(const char* base) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), 0, -1, 0x00020000);
+__device__ __forceinline__ Rsrc rsrc(const char* base, int num_records = -1) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), 0, num_records, 0x00020000);
 }
 constexpr int kNonTemporal = 2;  // cache policy of the stores: no reuse before the next launch
 
@@ -1076,9 +1078,14 @@ __device__ __forceinline__ void step_tile(const LatticeDesc* __restrict__ Ld, in
 // registers, two per register, for its relaxation one plane later), and the
 // plane after it, whose loads fly while the current plane is relaxed. One
 // barrier per plane separates a stage's reads from its reloading.
-// It applies to D3Q27 lattices whose n_x is a multiple of 64 and n_y a
-// multiple of TY (full tiles), x and z periodic; the others take the kernel
-// above.
+// It applies to D3Q27 lattices whose n_x is a multiple of 64, x and z
+// periodic, and y either bounce-back with n_y a multiple of TY or periodic
+// with n_y > TY / 2 (so that every staged row, y0 - 2 ... y0 + TY + 1, lies
+// within one period of the axis); the others take the kernel above. On a
+// periodic y axis whose n_y is not a multiple of TY the last tile row
+// overhangs it: its rows at and beyond n_y hold the wrapped rows 0, 1, ...
+// (staged like any other) and give the anomaly that the last real row takes
+// as its neighbour's; their stores are dropped.
 //
 // Stage layout (bytes): 27 boxes of BOX bytes, direction i's at i BOX. Box
 // row r (0 ... TY + 1) holds lattice row y0 - 1 - c_iy + r, so a node of tile
@@ -1130,7 +1137,7 @@ struct Held {
 // a wall takes the populations that would arrive through it from its own
 // post-collision populations of the opposite directions, loaded directly, and
 // the anomaly beyond the wall is the odd ghost -Q~ of the wall row.
-template <int S, bool FORCE, bool WALLY, bool DIAG>
+template <int S, bool FORCE, bool WALLY, bool DIAG, bool OVER>
 __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld, int64_t tl, int parity,
                                               unsigned char* __restrict__ smem, const DiagArgs& da,
                                               double* __restrict__ wslot) {
@@ -1162,7 +1169,9 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
   const int lx = tid & 63, ly = tid >> 6;
   const int gx = x0 + lx, gy = y0 + ly;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // a wave is one tile row: wall rows are wave-uniform
+  // a wave is one tile row: wall rows, and the rows of an overhanging last
+  // tile row (OVER, periodic y only) that lie beyond n_y, are wave-uniform
+  const bool live = !OVER || y0 + wave < k.n1;
   const bool wall_lo = WALLY && k.w1 && y0 == 0, wall_hi = WALLY && k.w1 && y0 + TY == k.n1;
   // +1: the populations with c_y = +1 arrive through the wall below, -1: those
   // with c_y = -1 through the wall above, 0: no wall next to this row
@@ -1194,7 +1203,8 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
     hslot = row * (TX + 2) + (side ? TX + 1 : 0);
     h_side = (wall_lo && row == 0) ? 1 : ((wall_hi && row == TY - 1) ? -1 : 0);
   }
-  // in-plane byte offsets of the node and of its halo node (bounce-back loads)
+  // in-plane byte offsets of the node (of its wrapped row beyond n_y) and of
+  // its halo node (bounce-back loads)
   const uint32_t own = uint32_t(gy * k.n0 + gx) * 2u;
   const int hgx = x0 + hx < 0 ? x0 + hx + k.n0 : (x0 + hx >= k.n0 ? x0 + hx - k.n0 : x0 + hx);
   const uint32_t hown = uint32_t((y0 + max(hy, 0)) * k.n0 + hgx) * 2u;
@@ -1373,10 +1383,12 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
     if constexpr (DIAG) {
       // the record's moments of plane z, from its held pulled values (here,
       // before the next plane's values are held too)
-      // (every lane holds a node: each field is folded as soon as it is formed)
-      diag_node<3>(da, [&](int i) { return Store<S>::to_float(cur.get(i)); }, gx, gy, z,
-                   int64_t(gx) + int64_t(k.n0) * (int64_t(gy) + int64_t(k.n1) * z),
-                   [&](int j, double v) { diag_fold_one(j, v, wslot); });
+      // (every lane of a live row holds a node: each field is folded as soon
+      // as it is formed)
+      if (live)
+        diag_node<3>(da, [&](int i) { return Store<S>::to_float(cur.get(i)); }, gx, gy, z,
+                     int64_t(gx) + int64_t(k.n0) * (int64_t(gy) + int64_t(k.n1) * z),
+                     [&](int j, double v) { diag_fold_one(j, v, wslot); });
     }
 
     // next plane: values (kept for its relaxation), own anomaly (closes the
@@ -1393,7 +1405,10 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
       const float qyp = wall_side == -1 ? -qc[1] : QY(b, syp);
       Gd[1] = (qyp - qym) * k.hil[1];
       Gd[2] = (qn[2] - qprev) * hz;
-      const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes);
+      // a row beyond n_y stores through a resource of no records: the
+      // hardware's range check drops every store (its values are the
+      // wrapped row's, which the first tile row stores)
+      const Rsrc rd = rsrc(dst + uint64_t(z) * k.slab_bytes, live ? -1 : 0);
       collide<3, FORCE, S == 0, false>(k, drho, dj, Gd, [&](int i) { return Store<S>::to_float(cur.get(i)); },
                         [&](int i, float o) { Store<S>::store(rd, own, i * sb, o); });
     }
@@ -1446,7 +1461,13 @@ __global__ void __launch_bounds__(lds::NT)
     const LatticeDesc* d = table + L;
     if (substep < d->nsteps) {
       const int parity = (d->parity0 + int(substep & 1)) & 1;
-      step_tile_lds<S, FORCE, WALLY, DIAG>(d, t - d->tile_base, parity, smem, da, wslot);
+      const int64_t tl = t - d->tile_base;
+      // a last tile row that overhangs a periodic y axis takes the variant
+      // whose rows beyond n_y store nothing; every other tile the plain one
+      if (!WALLY && d->n[1] % lds::TY != 0 && (tl / d->tiles[0]) % d->tiles[1] == d->tiles[1] - 1)
+        step_tile_lds<S, FORCE, WALLY, DIAG, !WALLY>(d, tl, parity, smem, da, wslot);
+      else
+        step_tile_lds<S, FORCE, WALLY, DIAG, false>(d, tl, parity, smem, da, wslot);
     }
     __syncthreads();
   }

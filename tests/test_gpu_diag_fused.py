@@ -38,8 +38,12 @@ CASES = {
                               mode=((2 * math.pi / 64, 0.0, 2 * math.pi / 24), (0.0, 1.0, 0.0))),
     "d3_channel_bf16_staged": dict(n=(128, 32, 12), lam=(2.0, 1.0, 1.0), T=0.5, omega=1.9, storage="bf16",
                                    walls=(False, True, False), force=(1e-5, 0.0, 0.0)),
+    # LDS-staged kernel, periodic y with n_y % 16 != 0: rows of the last tile
+    # row beyond the axis must add nothing to the record
+    "d3_overhang_f16_staged": dict(n=(64, 20, 10), lam=(1.0, 1.2, 1.0), T=0.5, omega=1.8, storage="f16",
+                                   mode=((0.0, 2 * math.pi / 20, 0.0), (1.0, 0.0, 0.0))),
 }
-STAGED = {"d3_box_f16_staged", "d3_channel_bf16_staged"}
+STAGED = {"d3_box_f16_staged", "d3_channel_bf16_staged", "d3_overhang_f16_staged"}
 
 
 def make(case, every, capacity=64, seed=0):

@@ -1,5 +1,6 @@
 """The LDS-staged D3Q27 step kernel (16-bit storage, n_x a multiple of 64,
-n_y a multiple of 16, x and z periodic, y periodic or bounce-back).
+x and z periodic, y bounce-back with n_y a multiple of 16 or periodic with
+n_y > 8: the last tile row may then overhang the axis).
 
 It pulls the same stored values as the register-pull kernel and runs the same
 per-node arithmetic, so the two agree to the last bit but for the rounding of
@@ -29,9 +30,20 @@ CASES = {
     "channel_walls_force": dict(n=(128, 32, 12), lam=(2.0, 1.0, 1.0), T=0.5, omega=1.9,
                                 walls=(False, True, False), force=(1e-5, 0.0, 0.0)),
     "walls_one_row": dict(n=(64, 16, 8), T=1 / 3, omega=1.4, walls=(False, True, False)),
+    # periodic y with n_y % 16 != 0: the last tile row overhangs the axis (8 of
+    # 16 rows beyond it; stretched, force on two axes)
+    "overhang_force": dict(n=(64, 24, 6), lam=(1.0, 1.4, 1.0), T=0.45, omega=1.7, force=(2e-5, 1e-5, 0.0)),
+    # the shortest axis the kernel takes: n_y = 9, one tile row of 9 live
+    # rows whose 18 staged rows span the axis twice
+    "overhang_short": dict(n=(128, 9, 4), T=0.5, omega=1.5),
+    # several tile rows and chunks, the last one overhanging by 8 rows
+    "overhang_stretched": dict(n=(64, 40, 9), lam=(2.0, 1.0, 1.0), T=0.5, omega=1.9),
 }
-# not eligible (n_y % 16 != 0; walls on x): take the register-pull kernel
-RAGGED = dict(n=(64, 8, 5), T=0.5, omega=1.5)
+# not eligible (n_x % 64 != 0; periodic y with n_y <= 8; walls on y with
+# n_y % 16 != 0; walls on x): take the register-pull kernel
+RAGGED = dict(n=(96, 16, 5), T=0.5, omega=1.5)
+SHORT_Y = dict(n=(64, 8, 5), T=0.5, omega=1.5)
+WALLS_RAGGED = dict(n=(64, 24, 5), T=0.5, omega=1.5, walls=(False, True, False))
 WALLS_X = dict(n=(64, 16, 6), T=0.5, omega=1.5, walls=(True, False, False))
 EPS = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
 
@@ -99,7 +111,7 @@ def test_staged_one_step_against_oracle(case, storage):
 
 
 def test_kernel_choice():
-    for case in (RAGGED, WALLS_X):
+    for case in (RAGGED, SHORT_Y, WALLS_RAGGED, WALLS_X):
         p = O.Params(**case)
         lat = lattice(p, "f16", True, random_state(p, seed=3))
         assert lat.kernel_info()["kernel"] == "register"
