@@ -379,8 +379,9 @@ typedef struct elbm_faces_s* elbm_faces_handle;
  * PERIODIC (fluid extents >= 3 there). A D3Q27 lattice takes the faces of a
  * channel: PERIODIC x faces, WALL y faces (one kind per face, node_kind
  * NULL; wall_velocity[2], [3]: the x-velocity of the low and the high wall),
- * z periodic, FP32 storage, u_adv = 0, all axes periodic in bc and n_y the
- * fluid rows (>= 3) plus 2 ghost rows. ELBM_EINVAL / ELBM_EUNSUPPORTED with
+ * z periodic, any storage (FP16 / BF16: the wall populations are rounded
+ * to the storage format like any stored value), u_adv = 0, all axes
+ * periodic in bc and n_y the fluid rows (>= 3) plus 2 ghost rows. ELBM_EINVAL / ELBM_EUNSUPPORTED with
  * a message otherwise. Host arithmetic only. */
 int32_t elbm_faces_query_bytes(elbm_handle lattice, const elbm_faces_params* fp, size_t* bytes);
 

@@ -1060,7 +1060,6 @@ bool face_odd(int kind) { return kind == ELBM_FACE_SYMMETRY || kind == ELBM_FACE
 // ghost row below and one above the fluid. Device bytes: the wall nodes'
 // pulled (rho, j_y).
 int32_t plan_walls3(const elbm_lattice* h, const elbm_faces_params* fp, size_t& bytes) {
-  if (h->p.storage != ELBM_STORE_F32) return fail(ELBM_EUNSUPPORTED, "Grad walls need FP32 storage");
   if (h->p.u_adv[0] != 0.0 || h->p.u_adv[1] != 0.0 || h->p.u_adv[2] != 0.0)
     return fail(ELBM_EUNSUPPORTED, "Grad walls need u_adv == 0 (rest reference)");
   for (int a = 0; a < 3; ++a)
@@ -1218,6 +1217,9 @@ int32_t elbm_faces_create(elbm_handle h, const elbm_faces_params* fp, void* dev_
     f->D = 3;
     Walls3Args& A = f->args3;
     A.pstride = h->pstride;
+    A.storage = h->p.storage;
+    A.scale = h->c64.scale;
+    A.inv_scale = h->c64.inv_scale;
     for (int a = 0; a < 3; ++a) {
       A.N[a] = int32_t(h->p.n[a]);
       A.n[a] = int32_t(h->p.n[a]) - (a == 1 ? 2 : 0);
@@ -1292,7 +1294,7 @@ int32_t elbm_faces_step(elbm_faces_handle f, int64_t nsteps) {
   if (s) return s;
   for (int64_t k = 0; k < nsteps; ++k) {
     if (f->D == 3) {
-      f->args3.h = static_cast<float*>(state_buf(h));
+      f->args3.h = state_buf(h);
       HIPCHK(launch_walls3(f->args3, h->stream));
     } else {
       f->args.h = static_cast<float*>(state_buf(h));

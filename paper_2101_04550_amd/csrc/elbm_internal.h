@@ -192,8 +192,11 @@ hipError_t launch_faces(const FaceArgs& a, hipStream_t st);
 // Grad's-approximation walls on the y faces of a D3Q27 lattice (x and z
 // periodic): the storage carries one ghost row below and one above the fluid.
 struct Walls3Args {
-  float* h;               // state buffer (FP32 deviations), plane slabs along z
+  void* h;                // state buffer (deviations in storage format), plane slabs along z
   int64_t pstride;
+  int32_t storage;        // ELBM_STORE_F32 / F16 / BF16
+  int32_t pad;
+  double scale, inv_scale;  // stored value = scale x deviation
   int32_t N[3];           // storage extents (n_y + 2 rows)
   int32_t n[3];           // fluid extents
   double lam[3], T, omega, omega_bulk, g[3];

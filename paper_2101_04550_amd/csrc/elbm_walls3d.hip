@@ -20,7 +20,9 @@
 //    the boundary row then sees an odd ghost, as next to a bounce-back wall.
 // Each ghost slot is written by one thread (A: the directions with c_y = s
 // of the row beyond the wall; B: the others), and neither kernel reads a
-// ghost row. FP64 arithmetic on the stored FP32 deviations.
+// ghost row. FP64 arithmetic on the stored deviations (FP32, or FP16 / BF16
+// storage, read exactly and rounded once when written).
+#include "elbm_codec.h"
 #include "elbm_internal.h"
 
 namespace elbm {
@@ -34,9 +36,12 @@ __device__ __forceinline__ double tri(int c, double u, double P, double lam) {
   return 0.5 * (c * u / lam + P / (lam * lam));
 }
 
+template <int S>
 struct View3 {
+  using T = typename Raw<S>::T;
   const Walls3Args& a;
-  __device__ explicit View3(const Walls3Args& args) : a(args) {}
+  T* const h;
+  __device__ explicit View3(const Walls3Args& args) : a(args), h(static_cast<T*>(args.h)) {}
   __device__ int wrap(int v, int ax) const {
     const int n = a.N[ax];
     v %= n;
@@ -45,8 +50,12 @@ struct View3 {
   __device__ int64_t idx(int X, int Y, int Z, int i) const {
     return (int64_t(wrap(Z, 2)) * 27 + i) * a.pstride + wrap(X, 0) + int64_t(a.N[0]) * wrap(Y, 1);
   }
-  __device__ double slot(int X, int Y, int Z, int i) const { return a.w[i] + double(a.h[idx(X, Y, Z, i)]); }
-  __device__ void set_slot(int X, int Y, int Z, int i, double f) const { a.h[idx(X, Y, Z, i)] = float(f - a.w[i]); }
+  __device__ double slot(int X, int Y, int Z, int i) const {
+    return a.w[i] + Raw<S>::get(h + idx(X, Y, Z, i)) * a.inv_scale;
+  }
+  __device__ void set_slot(int X, int Y, int Z, int i, double f) const {
+    Raw<S>::put(h + idx(X, Y, Z, i), (f - a.w[i]) * a.scale);
+  }
   // reported velocity (j' - rho g/2)/rho of the post-collision state at a storage node
   __device__ void velocity(int X, int Y, int Z, double (&u)[3]) const {
     double r = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -60,11 +69,12 @@ struct View3 {
 };
 
 // Kernel A: one thread per wall node, the low face (k < n_x n_z) then the high one.
+template <int S>
 __global__ void walls3_boundary_kernel(Walls3Args A) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t per = int64_t(A.n[0]) * A.n[2];
   if (k >= 2 * per) return;
-  const View3 v(A);
+  const View3<S> v(A);
   const int F = int(k / per);
   const int64_t r = k - F * per;
   const int X = int(r % A.n[0]), Z = int(r / A.n[0]);
@@ -98,8 +108,8 @@ __global__ void walls3_boundary_kernel(Walls3Args A) {
   double Pi[3][3];
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) {
-      const double S = grad[a][b] + grad[b][a];
-      Pi[a][b] = a == b ? kd * (S - m) + kb * m : kd * S;
+      const double sab = grad[a][b] + grad[b][a];
+      Pi[a][b] = a == b ? kd * (sab - m) + kb * m : kd * sab;
     }
   double P[3];
   for (int a = 0; a < 3; ++a) P[a] = A.T + ut[a] * ut[a] + Pi[a][a] / rt;
@@ -124,11 +134,12 @@ __global__ void walls3_boundary_kernel(Walls3Args A) {
 }
 
 // Kernel B: one thread per ghost node, the low ghost row (k < n_x n_z) then the high one.
+template <int S>
 __global__ void walls3_ghost_kernel(Walls3Args A) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t per = int64_t(A.n[0]) * A.n[2];
   if (k >= 2 * per) return;
-  const View3 v(A);
+  const View3<S> v(A);
   const int F = int(k / per);
   const int64_t r = k - F * per;
   const int X = int(r % A.n[0]), Z = int(r / A.n[0]);
@@ -158,17 +169,27 @@ __global__ void walls3_ghost_kernel(Walls3Args A) {
   }
 }
 
-}  // namespace
-
-hipError_t launch_walls3(const Walls3Args& A, hipStream_t st) {
+template <int S>
+hipError_t launch_s(const Walls3Args& A, hipStream_t st) {
   constexpr int NT = 128;
   const int64_t count = 2 * int64_t(A.n[0]) * A.n[2];
   const int blocks = int((count + NT - 1) / NT);
-  hipLaunchKernelGGL(walls3_boundary_kernel, dim3(blocks), dim3(NT), 0, st, A);
+  hipLaunchKernelGGL(walls3_boundary_kernel<S>, dim3(blocks), dim3(NT), 0, st, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(walls3_ghost_kernel, dim3(blocks), dim3(NT), 0, st, A);
+  hipLaunchKernelGGL(walls3_ghost_kernel<S>, dim3(blocks), dim3(NT), 0, st, A);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_walls3(const Walls3Args& A, hipStream_t st) {
+  switch (A.storage) {
+    case 0: return launch_s<0>(A, st);
+    case 1: return launch_s<1>(A, st);
+    case 2: return launch_s<2>(A, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace elbm

@@ -19,7 +19,16 @@ CASES = {
     # Sec. 3.5's stretched lattice with the multi-relaxation-time collision
     "stretched_mrt": dict(n=(16, 9, 8), lam=(1.4, 1.0, 2.0), T=0.55, omega=1.6, wall_u=(-0.01, 0.015),
                           rates=(1.2, 1.5)),
+    # 16-bit storage: FP16 on the LDS-staged kernel (n_x = 64; 22 storage rows,
+    # so the last tile row overhangs the periodic y axis), BF16 on the
+    # register-pull kernel
+    "f16_staged": dict(n=(64, 20, 6), lam=(1.4, 1.0, 1.0), T=0.55, omega=1.6, force=(1e-5, 0.0, 0.0),
+                       wall_u=(0.0, 0.02), storage="f16"),
+    "bf16_register": dict(n=(24, 10, 12), lam=(2.0, 1.0, 1.0), T=0.5, omega=1.9, force=(1e-5, 0.0, 0.0),
+                          wall_u=(0.0, 0.02), storage="bf16"),
 }
+# bound on the rel-L2 of the deviations after 20 steps (see test_walls_match_oracle)
+BOUND = {"f32": 1e-5, "f16": 2e-3, "bf16": 1.6e-2}
 
 
 def setup(case, seed=3):
@@ -40,7 +49,8 @@ def setup(case, seed=3):
     S[:] = w.reshape(27, 1, 1, 1)
     S[:, :, 1:ny + 1, :] = f0
     kw = dict(omega_bulk=rates[0], omega_ghost=rates[1]) if rates else {}
-    lat = E.Lattice(E.make_params((nx, ny + 2, nz), lam=lam, T=T, omega=omega, force=force, **kw))
+    lat = E.Lattice(E.make_params((nx, ny + 2, nz), lam=lam, T=T, omega=omega, force=force,
+                                  storage=c.get("storage", "f32"), **kw))
     lat.set_populations(S)
     walls = E.Faces(lat, ["periodic", "periodic", "wall", "wall"], wall_velocity=(0.0, 0.0) + tuple(c["wall_u"]))
     return p, f0, w, lat, walls, c["wall_u"], rates
@@ -49,18 +59,29 @@ def setup(case, seed=3):
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_walls_match_oracle(case):
     """20 steps from a seeded non-equilibrium state: fluid populations within
-    1e-5 rel-L2 of their deviations and 1e-6 absolute (FP32 storage)."""
+    1e-5 rel-L2 of their deviations and 1e-6 absolute with FP32 storage. With
+    16-bit storage every stored deviation is rounded each step, by at most
+    its unit roundoff u (2^-11 FP16, 2^-8 BF16) and u / sqrt(3) rms; with
+    omega near 2, which damps the non-equilibrium part little, 20 such
+    roundings add up like a random walk to about sqrt(20 / 3) u = 1.3e-3
+    (FP16) and 1.0e-2 (BF16) of the deviations: bounds 2e-3 and 1.6e-2. The
+    initial state is the stored (rounded) one on both sides."""
     p, f, w, lat, walls, wall_u, rates = setup(case)
+    storage = CASES[case].get("storage", "f32")
+    if storage != "f32":
+        f = lat.populations()[:, :, 1:p.n[1] + 1, :]  # the rounded initial state
+        assert lat.kernel_info()["kernel"] == ("staged" if storage == "f16" else "register")
     steps = 20
     walls.step(steps)
     g = lat.populations()[:, :, 1:p.n[1] + 1, :]
     f = OW.run(f, p, steps, wall_u=wall_u, rates=rates)
     W = w.reshape(27, 1, 1, 1)
     e = float(np.linalg.norm((g - f).ravel()) / np.linalg.norm((f - W).ravel()))
-    MEASURED.append(dict(test="walls3d_vs_oracle", case=case, storage="f32", component="dev_rel_l2", measured=e,
-                         target=1e-5, bound=1e-5))
-    assert e <= 1e-5, e
-    assert np.abs(g - f).max() <= 1e-6
+    MEASURED.append(dict(test="walls3d_vs_oracle", case=case, storage=storage, component="dev_rel_l2", measured=e,
+                         target=BOUND[storage], bound=BOUND[storage]))
+    assert e <= BOUND[storage], e
+    if storage == "f32":
+        assert np.abs(g - f).max() <= 1e-6
     walls.close()
     lat.close()
 
@@ -90,8 +111,8 @@ def test_couette_between_grad_walls_3d():
 
 def test_walls3d_reject_unsupported_lattices():
     E = lib()
-    lat16 = E.Lattice(E.make_params((8, 8, 8), T=1 / 3, omega=1.2, storage="f16"))
-    with pytest.raises(E.ElbmError) as ei:
+    lat16 = E.Lattice(E.make_params((8, 8, 8), T=1 / 3, omega=1.2, storage="f16", u_adv=(0.05, 0.0, 0.0)))
+    with pytest.raises(E.ElbmError) as ei:  # walls need the rest reference
         E.Faces(lat16, ["periodic", "periodic", "wall", "wall"])
     assert ei.value.status == E.EUNSUPPORTED
     latw = E.Lattice(E.make_params((8, 8, 8), T=1 / 3, omega=1.2, walls=(False, True, False)))
