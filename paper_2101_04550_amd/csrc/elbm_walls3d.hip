@@ -42,10 +42,11 @@ struct View3 {
   const Walls3Args& a;
   T* const h;
   __device__ explicit View3(const Walls3Args& args) : a(args), h(static_cast<T*>(args.h)) {}
+  // periodic index of a coordinate at most one period outside the storage
+  // (every caller offsets an in-range coordinate by -1, 0 or +1)
   __device__ int wrap(int v, int ax) const {
     const int n = a.N[ax];
-    v %= n;
-    return v < 0 ? v + n : v;
+    return v < 0 ? v + n : (v >= n ? v - n : v);
   }
   __device__ int64_t idx(int X, int Y, int Z, int i) const {
     return (int64_t(wrap(Z, 2)) * 27 + i) * a.pstride + wrap(X, 0) + int64_t(a.N[0]) * wrap(Y, 1);
@@ -59,6 +60,7 @@ struct View3 {
   // reported velocity (j' - rho g/2)/rho of the post-collision state at a storage node
   __device__ void velocity(int X, int Y, int Z, double (&u)[3]) const {
     double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int i = 0; i < 27; ++i) {
       const double f = slot(X, Y, Z, i);
       r += f;
@@ -69,8 +71,10 @@ struct View3 {
 };
 
 // Kernel A: one thread per wall node, the low face (k < n_x n_z) then the high one.
+constexpr int kWallThreads = 128;
+
 template <int S>
-__global__ void walls3_boundary_kernel(Walls3Args A) {
+__global__ void __launch_bounds__(kWallThreads) walls3_boundary_kernel(Walls3Args A) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t per = int64_t(A.n[0]) * A.n[2];
   if (k >= 2 * per) return;
@@ -85,6 +89,7 @@ __global__ void walls3_boundary_kernel(Walls3Args A) {
   v.velocity(X, Yf, Z, uf);
   for (int b = 0; b < 3; ++b) ut[b] = (2.0 * uw[b] + uf[b]) / 3.0;
   double S0 = 0.0, Sout = 0.0;
+  #pragma unroll
   for (int i = 0; i < 27; ++i) {
     const int cy = c3(i, 1);
     if (cy == s) continue;
@@ -114,6 +119,7 @@ __global__ void walls3_boundary_kernel(Walls3Args A) {
   double P[3];
   for (int a = 0; a < 3; ++a) P[a] = A.T + ut[a] * ut[a] + Pi[a][a] / rt;
   double rho_b = 0.0, jy_b = 0.0;
+  #pragma unroll
   for (int i = 0; i < 27; ++i) {
     const int cx = c3(i, 0), cy = c3(i, 1), cz = c3(i, 2);
     double f;
@@ -135,7 +141,7 @@ __global__ void walls3_boundary_kernel(Walls3Args A) {
 
 // Kernel B: one thread per ghost node, the low ghost row (k < n_x n_z) then the high one.
 template <int S>
-__global__ void walls3_ghost_kernel(Walls3Args A) {
+__global__ void __launch_bounds__(kWallThreads) walls3_ghost_kernel(Walls3Args A) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t per = int64_t(A.n[0]) * A.n[2];
   if (k >= 2 * per) return;
@@ -146,6 +152,7 @@ __global__ void walls3_ghost_kernel(Walls3Args A) {
   const int G = F == 0 ? 0 : A.n[1] + 1;
   const double rt = A.mom[2 * k], jt = -A.mom[2 * k + 1];  // odd ghost of the boundary node
   double su = 0.0, sju = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  #pragma unroll
   for (int i = 0; i < 27; ++i) {
     const int cy = c3(i, 1);
     const int Ys = v.wrap(G - cy, 1);
@@ -162,6 +169,7 @@ __global__ void walls3_ghost_kernel(Walls3Args A) {
   const double R = rt - su, J = jt / A.lam[1] - sju;
   const double det = s0 * s2 - s1 * s1;
   const double ca = (R * s2 - J * s1) / det, cb = (s0 * J - s1 * R) / det;
+  #pragma unroll
   for (int i = 0; i < 27; ++i) {
     const int cy = c3(i, 1);
     const int Ys = v.wrap(G - cy, 1);
@@ -171,7 +179,7 @@ __global__ void walls3_ghost_kernel(Walls3Args A) {
 
 template <int S>
 hipError_t launch_s(const Walls3Args& A, hipStream_t st) {
-  constexpr int NT = 128;
+  constexpr int NT = kWallThreads;
   const int64_t count = 2 * int64_t(A.n[0]) * A.n[2];
   const int blocks = int((count + NT - 1) / NT);
   hipLaunchKernelGGL(walls3_boundary_kernel<S>, dim3(blocks), dim3(NT), 0, st, A);
