@@ -35,6 +35,10 @@ def _mix():
     out.append((p, I.uniform((128, 16, 12), u0=(0.01, -0.02, 0.005)), "f16"))
     p = O.Params(n=(64, 16, 20), T=1 / 3, omega=1.3, force=(1e-4, -2e-4, 5e-5))
     out.append((p, I.uniform((64, 16, 20), u0=(0.0, 0.01, 0.0)), "bf16"))
+    # the staged class again, n_y = 24: its last tile row overhangs the periodic
+    # y axis (the tile variant chosen per tile, behind other lattices' tiles)
+    p = O.Params(n=(64, 24, 10), lam=(1.0, 1.5, 1.0), T=0.5, omega=1.75)
+    out.append((p, I.channel_field((64, 24, 10), (1.0, 1.5, 1.0), seed_offset=14), "f16"))
     return out
 
 
@@ -46,7 +50,7 @@ def _make(mix):
 def test_batch_equals_alone_bitwise(use_graph):
     E = lib()
     mix = _mix()
-    steps = [7, 12, 3, 12, 9, 1, 5, 12, 8]
+    steps = [7, 12, 3, 12, 9, 1, 5, 12, 8, 6]
     alone = _make(mix)
     for lat, k in zip(alone, steps):
         lat.step(k)
@@ -68,7 +72,7 @@ def test_batch_matches_oracle():
     and 1e-2 (BF16)."""
     E = lib()
     mix = _mix()
-    steps = [7, 12, 3, 12, 9, 1, 5, 12, 8]
+    steps = [7, 12, 3, 12, 9, 1, 5, 12, 8, 6]
     lats = _make(mix)
     f0 = [lat.populations() for lat in lats]
     b = E.Batch(len(lats))
@@ -92,7 +96,7 @@ def test_graph_reuse_across_mixes_and_continuation():
     run followed by solo steps continues the same trajectory."""
     E = lib()
     mix = _mix()
-    total = [20] * 9
+    total = [20] * 10
     alone = _make(mix)
     for lat, k in zip(alone, total):
         lat.step(k)
@@ -100,8 +104,8 @@ def test_graph_reuse_across_mixes_and_continuation():
     lats = _make(mix)
     b = E.Batch(len(lats))
     # three rounds of at most 8 steps; lattices drop in and out of the mix
-    b.run(lats, [8, 8, 0, 8, 3, 8, 8, 0, 5], use_graph=True)
-    b.run(lats, [8, 5, 8, 8, 8, 8, 8, 8, 8], use_graph=True)
+    b.run(lats, [8, 8, 0, 8, 3, 8, 8, 0, 5, 8], use_graph=True)
+    b.run(lats, [8, 5, 8, 8, 8, 8, 8, 8, 8, 4], use_graph=True)
     done = [lat.step_count for lat in lats]
     b.run(lats[::-1], [min(8, 20 - d) for d in done[::-1]], use_graph=True)
     for lat in lats:
