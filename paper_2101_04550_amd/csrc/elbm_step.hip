@@ -1203,8 +1203,9 @@ __device__ __forceinline__ void step_tile_lds(const LatticeDesc* __restrict__ Ld
     hslot = row * (TX + 2) + (side ? TX + 1 : 0);
     h_side = (wall_lo && row == 0) ? 1 : ((wall_hi && row == TY - 1) ? -1 : 0);
   }
-  // in-plane byte offsets of the node (of its wrapped row beyond n_y) and of
-  // its halo node (bounce-back loads)
+  // in-plane byte offsets of the node and of its halo node (bounce-back
+  // loads); a row beyond n_y has an offset past the plane, used only by its
+  // stores, which are dropped
   const uint32_t own = uint32_t(gy * k.n0 + gx) * 2u;
   const int hgx = x0 + hx < 0 ? x0 + hx + k.n0 : (x0 + hx >= k.n0 ? x0 + hx - k.n0 : x0 + hx);
   const uint32_t hown = uint32_t((y0 + max(hy, 0)) * k.n0 + hgx) * 2u;
