@@ -373,7 +373,8 @@ typedef struct elbm_faces_params {
 typedef struct elbm_faces_s* elbm_faces_handle;
 
 /* Device bytes of the face tables of `lattice` (node lists, ghost list,
- * per-node moments). The lattice must be D2Q9 with FP32 storage, u_adv = 0
+ * per-node moments). The lattice must be D2Q9 (any storage: FP16 / BF16
+ * face values are rounded to the storage format like any stored value), u_adv = 0
  * and both axes periodic (bc), and it must carry the ghost ring: its
  * extents are the fluid extents plus 2 along every axis whose faces are not
  * PERIODIC (fluid extents >= 3 there). A D3Q27 lattice takes the faces of a

@@ -1081,7 +1081,6 @@ int32_t plan_faces(const elbm_lattice* h, const elbm_faces_params* fp, FacePlan&
   if (!h || !fp) return fail(ELBM_EINVAL, "NULL argument");
   if (fp->abi_version != ELBM_ABI_VERSION) return fail(ELBM_EINVAL, "faces abi_version mismatch");
   if (h->D != 2) return fail(ELBM_EUNSUPPORTED, "open faces are implemented for D2Q9 lattices only");
-  if (h->p.storage != ELBM_STORE_F32) return fail(ELBM_EUNSUPPORTED, "open faces need FP32 storage");
   if (h->p.u_adv[0] != 0.0 || h->p.u_adv[1] != 0.0)
     return fail(ELBM_EUNSUPPORTED, "open faces need u_adv == 0 (rest reference)");
   if (h->p.bc[0] != ELBM_BC_PERIODIC || h->p.bc[1] != ELBM_BC_PERIODIC)
@@ -1259,6 +1258,9 @@ int32_t elbm_faces_create(elbm_handle h, const elbm_faces_params* fp, void* dev_
   f->h = h;
   FaceArgs& A = f->args;
   A.pstride = h->pstride;
+  A.storage = h->p.storage;
+  A.scale = h->c64.scale;
+  A.inv_scale = h->c64.inv_scale;
   for (int a = 0; a < 2; ++a) {
     A.N[a] = int32_t(h->p.n[a]);
     A.o[a] = P.o[a];
@@ -1297,7 +1299,7 @@ int32_t elbm_faces_step(elbm_faces_handle f, int64_t nsteps) {
       f->args3.h = state_buf(h);
       HIPCHK(launch_walls3(f->args3, h->stream));
     } else {
-      f->args.h = static_cast<float*>(state_buf(h));
+      f->args.h = state_buf(h);
       HIPCHK(launch_faces(f->args, h->stream));
     }
     s = elbm_step(h, 1);

@@ -1,4 +1,4 @@
-// Open boundaries of a D2Q9 lattice (FP32 deviation storage): Grad's-
+// Open boundaries of a D2Q9 lattice (FP32, FP16 or BF16 deviation storage): Grad's-
 // approximation walls, symmetry planes, velocity inlets and outlets.
 //
 // The lattice the step kernel advances is periodic and carries one ring of
@@ -37,9 +37,11 @@
 //  OUTLET    f_i = f^eq_i(rho_out, u_f) + f_i(x_f) - f^eq_i(rho_f, u_f): the
 //            prescribed density with the inward neighbour's velocity and
 //            non-equilibrium part.
-// All of it in FP64 from the stored FP32 deviations; a population is written
-// back rounded to FP32 as a deviation from the reference weight.
+// All of it in FP64 from the stored deviations (read exactly); a population
+// is written back as a deviation from the reference weight, rounded once to
+// the storage format.
 #include "elbm.h"
+#include "elbm_codec.h"
 #include "elbm_internal.h"
 
 namespace elbm {
@@ -54,9 +56,12 @@ __device__ __forceinline__ double tri(int c, double u, double P, double lam) {
   return 0.5 * (c * u / lam + P / (lam * lam));
 }
 
+template <int S>
 struct View {
+  using T = typename Raw<S>::T;
   const FaceArgs& a;
-  __device__ explicit View(const FaceArgs& args) : a(args) {}
+  T* const h;
+  __device__ explicit View(const FaceArgs& args) : a(args), h(static_cast<T*>(args.h)) {}
   __device__ int wrap(int v, int ax) const {
     const int n = a.N[ax];
     v %= n;
@@ -65,10 +70,10 @@ struct View {
   __device__ int64_t idx(int X, int Y, int i) const { return (int64_t(Y) * 9 + i) * a.pstride + X; }
   // population i stored at storage node (X, Y) (wrapped)
   __device__ double slot(int X, int Y, int i) const {
-    return a.w[i] + double(a.h[idx(wrap(X, 0), wrap(Y, 1), i)]);
+    return a.w[i] + Raw<S>::get(h + idx(wrap(X, 0), wrap(Y, 1), i)) * a.inv_scale;
   }
   __device__ void set_slot(int X, int Y, int i, double f) const {
-    a.h[idx(wrap(X, 0), wrap(Y, 1), i)] = float(f - a.w[i]);
+    Raw<S>::put(h + idx(wrap(X, 0), wrap(Y, 1), i), (f - a.w[i]) * a.scale);
   }
   // fluid coordinates -> storage coordinates
   __device__ int SX(int x) const { return x + a.o[0]; }
@@ -92,7 +97,8 @@ struct View {
 };
 
 // Rule of a boundary node: fills fm[i] for its missing directions.
-__device__ void boundary_rule(const View& v, const FaceNode& nd, double (&fm)[9], bool (&miss)[9]) {
+template <int S>
+__device__ void boundary_rule(const View<S>& v, const FaceNode& nd, double (&fm)[9], bool (&miss)[9]) {
   const FaceArgs& A = v.a;
   const int x = nd.x, y = nd.y, F = nd.face, kind = nd.kind;
   const int n_ax = F >> 1, t_ax = 1 - n_ax;
@@ -170,10 +176,11 @@ __device__ void boundary_rule(const View& v, const FaceNode& nd, double (&fm)[9]
 }
 
 // Kernel A: one thread per boundary node of [first, first + count).
+template <int S>
 __global__ void faces_boundary_kernel(FaceArgs A, int first, int count) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= count) return;
-  const View v(A);
+  const View<S> v(A);
   const FaceNode nd = A.nodes[first + k];
   double fm[9];
   bool miss[9];
@@ -204,10 +211,11 @@ __global__ void faces_boundary_kernel(FaceArgs A, int first, int count) {
 // Kernel B: one thread per ghost node: its populations that come from other
 // ghost nodes are set to w_i (a + b c_in) so that, with those that come from
 // fluid nodes, its pulled density and normal momentum hit the targets.
+template <int S>
 __global__ void faces_ghost_kernel(FaceArgs A) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= A.n_ghost) return;
-  const View v(A);
+  const View<S> v(A);
   const FaceGhost gh = A.ghosts[k];
   const int ax = gh.axis;
   double rt = 1.0, jt = 0.0;
@@ -241,26 +249,37 @@ __global__ void faces_ghost_kernel(FaceArgs A) {
     if (ctl[i]) v.set_slot(gh.X - cdir(i, 0), gh.Y - cdir(i, 1), i, A.w[i] * (ca + cb * cdir(i, ax)));
 }
 
-}  // namespace
-
-hipError_t launch_faces(const FaceArgs& A, hipStream_t st) {
+template <int S>
+hipError_t launch_s(const FaceArgs& A, hipStream_t st) {
   constexpr int NT = 128;
   if (A.n_single > 0) {
-    hipLaunchKernelGGL(faces_boundary_kernel, dim3((A.n_single + NT - 1) / NT), dim3(NT), 0, st, A, 0, A.n_single);
+    hipLaunchKernelGGL(faces_boundary_kernel<S>, dim3((A.n_single + NT - 1) / NT), dim3(NT), 0, st, A, 0,
+                       A.n_single);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (A.n_corner > 0) {
-    hipLaunchKernelGGL(faces_boundary_kernel, dim3((A.n_corner + NT - 1) / NT), dim3(NT), 0, st, A, A.n_single,
+    hipLaunchKernelGGL(faces_boundary_kernel<S>, dim3((A.n_corner + NT - 1) / NT), dim3(NT), 0, st, A, A.n_single,
                        A.n_corner);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (A.n_ghost > 0) {
-    hipLaunchKernelGGL(faces_ghost_kernel, dim3((A.n_ghost + NT - 1) / NT), dim3(NT), 0, st, A);
+    hipLaunchKernelGGL(faces_ghost_kernel<S>, dim3((A.n_ghost + NT - 1) / NT), dim3(NT), 0, st, A);
     return hipGetLastError();
   }
   return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_faces(const FaceArgs& A, hipStream_t st) {
+  switch (A.storage) {
+    case 0: return launch_s<0>(A, st);
+    case 1: return launch_s<1>(A, st);
+    case 2: return launch_s<2>(A, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace elbm

@@ -168,8 +168,11 @@ struct FaceGhost {
   double parity;
 };
 struct FaceArgs {
-  float* h;               // state buffer (FP32 deviations), plane slabs along y
+  void* h;                // state buffer (deviations in storage format), plane slabs along y
   int64_t pstride;
+  int32_t storage;        // ELBM_STORE_F32 / F16 / BF16
+  int32_t spad;
+  double scale, inv_scale;  // stored value = scale x deviation
   int32_t N[2];           // storage extents (fluid + ghost ring on open axes)
   int32_t o[2];           // 1 on an open axis (ghost ring), 0 on a periodic one
   int32_t n[2];           // fluid extents

@@ -1,4 +1,5 @@
-"""Open boundaries on the GPU (elbm_faces_*, D2Q9 FP32) against the
+"""Open boundaries on the GPU (elbm_faces_*, D2Q9; FP32, and FP16 / BF16
+storage on the flat plate's faces) against the
 open-boundary oracle (oracle/elbm_faces.py): Grad's-approximation walls
 (resting and moving), symmetry planes, inlets, outlets and their corners, on
 cubic and stretched lattices, with and without a body force."""
@@ -29,7 +30,7 @@ CASES = {
 }
 
 
-def setup(case, seed=1, rates=None):
+def setup(case, seed=1, rates=None, storage="f32"):
     E = lib()
     c = CASES[case]
     n, lam, T, omega = c["n"], c["lam"], c["T"], c["omega"]
@@ -50,7 +51,7 @@ def setup(case, seed=1, rates=None):
     S[:] = w.reshape(9, 1, 1)
     S[:, o[1]:o[1] + n[1], o[0]:o[0] + n[0]] = f0
     kw = dict(omega_bulk=rates[0], omega_ghost=rates[1]) if rates else {}
-    lat = E.Lattice(E.make_params(N, lam=lam, T=T, omega=omega, force=force, **kw))
+    lat = E.Lattice(E.make_params(N, lam=lam, T=T, omega=omega, force=force, storage=storage, **kw))
     lat.set_populations(S)
     faces = E.Faces(lat, [fc.node_kind[F].tolist() if not fc.periodic(F // 2) else "periodic" for F in range(4)],
                     wall_velocity=wall, inlet_velocity=(inlet,) * 4)
@@ -119,10 +120,34 @@ def test_couette_between_grad_walls_on_gpu():
     lat.close()
 
 
+@pytest.mark.parametrize("storage,bound", [("f16", 2e-3), ("bf16", 1.6e-2)])
+@pytest.mark.parametrize("case", ["plate", "channel_force"])
+def test_faces_with_16_bit_storage_match_oracle(case, storage, bound):
+    """The face kernels read the stored 16-bit deviations exactly and round
+    what they write once: 20 steps from the stored (rounded) initial state
+    against the FP64 oracle, deviations rel-L2 within the bound of 20
+    roundings at the format's unit roundoff u (2^-11 FP16, 2^-8 BF16, u /
+    sqrt(3) rms each, adding up to about sqrt(20 / 3) u: 1.3e-3 / 1.0e-2)."""
+    p, fc, o, _, w, lat, faces = setup(case, storage=storage)
+    f = lat.populations()[:, o[1]:o[1] + p.n[1], o[0]:o[0] + p.n[0]]
+    steps = 20
+    faces.step(steps)
+    g = lat.populations()[:, o[1]:o[1] + p.n[1], o[0]:o[0] + p.n[0]]
+    for _ in range(steps):
+        f = OF.step_open(f, p, fc)
+    W = w.reshape(9, 1, 1)
+    e = float(np.linalg.norm((g - f).ravel()) / np.linalg.norm((f - W).ravel()))
+    MEASURED.append(dict(test="faces_vs_oracle", case=case, storage=storage, component="dev_rel_l2", measured=e,
+                         target=bound, bound=bound))
+    assert e <= bound, e
+    faces.close()
+    lat.close()
+
+
 def test_faces_reject_unsupported_lattices():
     E = lib()
-    lat16 = E.Lattice(E.make_params((8, 8), T=1 / 3, omega=1.2, storage="f16"))
-    with pytest.raises(E.ElbmError) as ei:
+    lat16 = E.Lattice(E.make_params((8, 8), T=1 / 3, omega=1.2, storage="f16", u_adv=(0.05, 0.0)))
+    with pytest.raises(E.ElbmError) as ei:  # faces need the rest reference
         E.Faces(lat16, ["inlet", "outlet", "wall", "wall"])
     assert ei.value.status == E.EUNSUPPORTED
     latw = E.Lattice(E.make_params((8, 8), T=1 / 3, omega=1.2, walls=(False, True)))
