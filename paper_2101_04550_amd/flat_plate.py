@@ -129,7 +129,7 @@ def analyse(u, c):
     return out
 
 
-def run(lam_x, steps, check_every=5000, out=None, scale=1, avg_from=0.5):
+def run(lam_x, steps, check_every=5000, out=None, scale=1, avg_from=0.5, storage="f32"):
     import torch  # noqa: F401
 
     from . import elbm as E
@@ -137,7 +137,7 @@ def run(lam_x, steps, check_every=5000, out=None, scale=1, avg_from=0.5):
     c = setup(lam_x, scale)
     nx, ny = c["nx"], c["ny"]
     N = (nx + 2, ny + 2)
-    lat = E.Lattice(E.make_params(N, lam=c["lam"], T=c["T"], omega=c["omega"]))
+    lat = E.Lattice(E.make_params(N, lam=c["lam"], T=c["T"], omega=c["omega"], storage=storage))
     rho = np.ones((N[1], N[0]))
     u0 = np.zeros((2, N[1], N[0]))
     u0[0] = c["u_inf"]
@@ -165,7 +165,7 @@ def run(lam_x, steps, check_every=5000, out=None, scale=1, avg_from=0.5):
     faces.close()
     lat.close()
     mean = acc / nacc
-    res = dict(lambda_x=lam_x, scale=scale, nodes=[nx, ny], T=c["T"], u_inf=c["u_inf"], nu=c["nu"], omega=c["omega"],
+    res = dict(lambda_x=lam_x, scale=scale, storage=storage, nodes=[nx, ny], T=c["T"], u_inf=c["u_inf"], nu=c["nu"], omega=c["omega"],
                x_leading_edge=c["x_le"], plate_length=c["L"], steps=steps, samples_averaged=nacc,
                last_vs_mean=float(np.abs(prev - mean).max() / c["u_inf"]), history=hist)
     res.update(analyse(mean, c))
@@ -184,8 +184,9 @@ def main(argv=None):
     ap.add_argument("--scale", type=int, default=1)
     ap.add_argument("--avg-from", type=float, default=0.5, help="average the fields over the checks after this fraction")
     ap.add_argument("--out", default="flat_plate.json")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     a = ap.parse_args(argv)
-    run(a.lambda_x, a.steps, a.check_every, a.out, a.scale, a.avg_from)
+    run(a.lambda_x, a.steps, a.check_every, a.out, a.scale, a.avg_from, a.storage)
 
 
 if __name__ == "__main__":
