@@ -1058,7 +1058,7 @@ bool face_odd(int kind) { return kind == ELBM_FACE_SYMMETRY || kind == ELBM_FACE
 
 // D3Q27: Grad walls on both y faces, x and z periodic; the storage carries one
 // ghost row below and one above the fluid. Device bytes: the wall nodes'
-// pulled (rho, j_y).
+// pulled (rho, j_y), then their inward neighbours' velocities.
 int32_t plan_walls3(const elbm_lattice* h, const elbm_faces_params* fp, size_t& bytes) {
   if (h->p.u_adv[0] != 0.0 || h->p.u_adv[1] != 0.0 || h->p.u_adv[2] != 0.0)
     return fail(ELBM_EUNSUPPORTED, "Grad walls need u_adv == 0 (rest reference)");
@@ -1073,7 +1073,8 @@ int32_t plan_walls3(const elbm_lattice* h, const elbm_faces_params* fp, size_t& 
   if (h->p.n[1] < 5) return fail(ELBM_EINVAL, "n_y must be the fluid rows (>= 3) plus 2 ghost rows");
   if (!std::isfinite(fp->wall_velocity[2]) || !std::isfinite(fp->wall_velocity[3]))
     return fail(ELBM_EINVAL, "wall velocities must be finite");
-  bytes = align_up(size_t(2) * size_t(h->p.n[0]) * size_t(h->p.n[2]) * 2 * sizeof(double), kAlign);
+  const size_t nodes = size_t(2) * size_t(h->p.n[0]) * size_t(h->p.n[2]);
+  bytes = align_up(nodes * 2 * sizeof(double), kAlign) + align_up(nodes * 3 * sizeof(double), kAlign);
   return ELBM_OK;
 }
 
@@ -1232,6 +1233,8 @@ int32_t elbm_faces_create(elbm_handle h, const elbm_faces_params* fp, void* dev_
     A.wall_u[0] = fp->wall_velocity[2];
     A.wall_u[1] = fp->wall_velocity[3];
     A.mom = static_cast<double*>(dev_buf);
+    A.uin = reinterpret_cast<double*>(static_cast<char*>(dev_buf) +
+                                      align_up(size_t(2) * size_t(A.n[0]) * size_t(A.n[2]) * 2 * sizeof(double), kAlign));
     *out = f;
     return ELBM_OK;
   }

@@ -206,6 +206,7 @@ struct Walls3Args {
   double w[27];           // reference weights of the deviations
   double wall_u[2];       // x-velocity of the low and the high wall
   double* mom;            // 2 doubles per wall node (pulled rho, j_y), low face then high face
+  double* uin;            // 3 doubles per wall node: velocity of its inward neighbour
 };
 hipError_t launch_walls3(const Walls3Args& a, hipStream_t st);
 

@@ -3,7 +3,9 @@
 // channel geometry of Sec. 3.5. The three-dimensional form of the D2Q9 wall
 // of elbm_faces.hip. The fluid rows are storage rows 1 .. n_y; rows 0 and
 // n_y + 1 are ghost rows that the step kernel pulls from, rewritten before
-// every step by two kernels:
+// every step by three kernels:
+//  U (one thread per wall node) records the reported velocity u_f of the
+//    node's inward neighbour;
 //  A (one thread per wall node) sets the populations a boundary node pulls
 //    from beyond its wall (c_y = s, s = +1 at the low wall, -1 at the high
 //    one) to Grad's approximation at the target velocity u_t = (2 u_w + u_f)/3
@@ -19,8 +21,8 @@
 //    rho and -j_y of the boundary node it faces: the anomaly difference at
 //    the boundary row then sees an odd ghost, as next to a bounce-back wall.
 // Each ghost slot is written by one thread (A: the directions with c_y = s
-// of the row beyond the wall; B: the others), and neither kernel reads a
-// ghost row. FP64 arithmetic on the stored deviations (FP32, or FP16 / BF16
+// of the row beyond the wall; B: the others), and no kernel reads a ghost
+// row. FP64 arithmetic on the stored deviations (FP32, or FP16 / BF16
 // storage, read exactly and rounded once when written).
 #include "elbm_codec.h"
 #include "elbm_internal.h"
@@ -73,6 +75,24 @@ struct View3 {
 // Kernel A: one thread per wall node, the low face (k < n_x n_z) then the high one.
 constexpr int kWallThreads = 128;
 
+// Kernel U: one thread per wall node (indexed as in kernel A), the reported
+// velocity of its inward neighbour, which kernel A reads for the node itself
+// and for its four neighbours along the wall.
+template <int S>
+__global__ void __launch_bounds__(kWallThreads) walls3_inward_kernel(Walls3Args A) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per = int64_t(A.n[0]) * A.n[2];
+  if (k >= 2 * per) return;
+  const View3<S> v(A);
+  const int F = int(k / per);
+  const int64_t r = k - F * per;
+  const int X = int(r % A.n[0]), Z = int(r / A.n[0]);
+  const int Yf = F == 0 ? 2 : A.n[1] - 1;
+  double u[3];
+  v.velocity(X, Yf, Z, u);
+  for (int b = 0; b < 3; ++b) A.uin[3 * k + b] = u[b];
+}
+
 template <int S>
 __global__ void __launch_bounds__(kWallThreads) walls3_boundary_kernel(Walls3Args A) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -84,9 +104,15 @@ __global__ void __launch_bounds__(kWallThreads) walls3_boundary_kernel(Walls3Arg
   const int X = int(r % A.n[0]), Z = int(r / A.n[0]);
   const int s = F == 0 ? 1 : -1;
   const int Y = F == 0 ? 1 : A.n[1];  // storage row of the boundary node
-  const int Yf = Y + s;               // its inward neighbour
   double uf[3], uw[3] = {F == 0 ? A.wall_u[0] : A.wall_u[1], 0.0, 0.0}, ut[3];
-  v.velocity(X, Yf, Z, uf);
+  // inward-row velocity of wall node (x, z) of this face, from kernel U
+  auto inward = [&](int x, int z, double (&u)[3]) {
+    x = x < 0 ? x + A.n[0] : (x >= A.n[0] ? x - A.n[0] : x);
+    z = z < 0 ? z + A.n[2] : (z >= A.n[2] ? z - A.n[2] : z);
+    const double* q = A.uin + 3 * (F * per + int64_t(z) * A.n[0] + x);
+    for (int b = 0; b < 3; ++b) u[b] = q[b];
+  };
+  inward(X, Z, uf);
   for (int b = 0; b < 3; ++b) ut[b] = (2.0 * uw[b] + uf[b]) / 3.0;
   double S0 = 0.0, Sout = 0.0;
   #pragma unroll
@@ -101,11 +127,11 @@ __global__ void __launch_bounds__(kWallThreads) walls3_boundary_kernel(Walls3Arg
   // grad[a][b] = d u_b / d x_a
   double grad[3][3], up[3], um[3];
   for (int b = 0; b < 3; ++b) grad[1][b] = s * (uf[b] - uw[b]) / (1.5 * A.lam[1]);
-  v.velocity(X + 1, Yf, Z, up);
-  v.velocity(X - 1, Yf, Z, um);
+  inward(X + 1, Z, up);
+  inward(X - 1, Z, um);
   for (int b = 0; b < 3; ++b) grad[0][b] = (up[b] - um[b]) / (2.0 * A.lam[0]) / 3.0;
-  v.velocity(X, Yf, Z + 1, up);
-  v.velocity(X, Yf, Z - 1, um);
+  inward(X, Z + 1, up);
+  inward(X, Z - 1, um);
   for (int b = 0; b < 3; ++b) grad[2][b] = (up[b] - um[b]) / (2.0 * A.lam[2]) / 3.0;
   // Pi_neq = -rho_t T (S_dev / omega + S_iso / omega_bulk), S_iso = (tr S / 3) I
   const double m = 2.0 * (grad[0][0] + grad[1][1] + grad[2][2]) / 3.0;
@@ -182,8 +208,11 @@ hipError_t launch_s(const Walls3Args& A, hipStream_t st) {
   constexpr int NT = kWallThreads;
   const int64_t count = 2 * int64_t(A.n[0]) * A.n[2];
   const int blocks = int((count + NT - 1) / NT);
-  hipLaunchKernelGGL(walls3_boundary_kernel<S>, dim3(blocks), dim3(NT), 0, st, A);
+  hipLaunchKernelGGL(walls3_inward_kernel<S>, dim3(blocks), dim3(NT), 0, st, A);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(walls3_boundary_kernel<S>, dim3(blocks), dim3(NT), 0, st, A);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(walls3_ghost_kernel<S>, dim3(blocks), dim3(NT), 0, st, A);
   return hipGetLastError();
