@@ -341,9 +341,10 @@ def _face_kind(k):
 
 
 class Faces:
-    """Open boundaries (elbm_faces_*) of a D2Q9 FP32 lattice that carries a
+    """Open boundaries (elbm_faces_*) of a D2Q9 lattice that carries a
     ghost ring on each non-periodic axis (its extents are the fluid extents
-    plus 2 there), or Grad walls on the y faces of a D3Q27 FP32 channel
+    plus 2 there), or Grad walls on the y faces of a D3Q27 channel (any
+    storage format)
     (kinds ["periodic", "periodic", "wall", "wall"], n_y = fluid rows + 2;
     wall_velocity[2], [3]: the walls' x-velocities).
 
